@@ -1,0 +1,268 @@
+"""Plain CPU oracle for the level-blocked MPK (arXiv 2205.01598).
+
+TEST INFRASTRUCTURE ONLY.  Nothing here is on the product path; the product
+library must never import this module.  It is slow on purpose: plain loops in
+C (``oracle.c``) and plain Python/numpy, FP64 throughout unless a function says
+otherwise, with no blocking, fusion or reordering beyond what the paper's
+definition states.
+
+Functions and the passages they follow
+  spmv_powers        Sec. 3 / Sec. 3.1 (Fig. 2): the MPK computes y_p = A^p x
+                     for p = 1..p_m and stores every y_p; the baseline is p_m
+                     back-to-back CRS SpMVs.  This is the exact target every
+                     MPK variant must reproduce (level blocking only reorders
+                     these operations, Sec. 4.2).
+  spmv_powers_lowp   the same product with matrix values stored in FP32 or
+                     BF16 and FP32 accumulation (an extension, not in the
+                     paper; parity for it is tolerance-based, not exact).
+  bfs_levels         Eq. (3) levels and the Sec. 4.1 renumbering (levels
+                     numbered consecutively, L(i-1) before L(i)).
+  peripheral_root    root choice for Eq. (3); the paper uses vertex 0 in its
+                     example (Sec. 4.1) and leaves the choice open otherwise.
+  level_nnz          nonzeros per level, the N_nz(T) of Eq. (5).
+  level_groups       greedy level groups of Sec. 4.3, criterion Eq. (5).
+  lp_schedule        diagonal traversal of the Lp diagram, Sec. 4.2 / Fig. 6.
+  cheb_coefficients  Chebyshev expansion coefficients of exp(-i H dt)
+                     (Sec. 7, Eq. (6)-(8); the coefficient formula is the
+                     standard Jacobi-Anger expansion the paper cites).
+  cheb_propagate     one Chebyshev time step, Eq. (7)-(8).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    lib.orc_spmv_powers.restype = ctypes.c_int
+    lib.orc_spmv_powers.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
+                                    ctypes.c_int32, _f64p, _f64p]
+    lib.orc_spmv_powers_lowp.restype = ctypes.c_int
+    lib.orc_spmv_powers_lowp.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]
+    lib.orc_bfs_distances.restype = ctypes.c_int
+    lib.orc_bfs_distances.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i64p]
+    lib.orc_peripheral_root.restype = ctypes.c_int64
+    lib.orc_peripheral_root.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64]
+    lib.orc_bfs_levels.restype = ctypes.c_int64
+    lib.orc_bfs_levels.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i32p, _i64p]
+    _lib = lib
+    return lib
+
+
+def _arrs(A):
+    rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    return rowptr, col, val
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+# ----------------------------------------------------------------------------
+# powers
+# ----------------------------------------------------------------------------
+
+def spmv_powers(A, x, p: int) -> np.ndarray:
+    """y_q = A y_{q-1}, y_0 = x, for q = 1..p (Sec. 3.1, Fig. 2), FP64.
+
+    ``x`` has shape (n,) or (n, k) (k right-hand sides, row-major).  Returns an
+    array of shape (p, n) or (p, n, k) holding y_1..y_p.
+    """
+    rowptr, col, val = _arrs(A)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    k = 1 if x.ndim == 1 else x.shape[1]
+    y = np.empty((p, A.n * k), dtype=np.float64)
+    rc = _load().orc_spmv_powers(A.n, _p(rowptr, _i64p), _p(col, _i32p), _p(val, _f64p),
+                                 k, p, _p(x, _f64p), _p(y, _f64p))
+    if rc != 0:
+        raise ValueError("orc_spmv_powers failed")
+    return y.reshape((p, A.n) if x.ndim == 1 else (p, A.n, k))
+
+
+def spmv_powers_lowp(A, x, p: int, vdtype: str) -> np.ndarray:
+    """Mixed-precision powers: values rounded to ``vdtype`` ('f32' or 'bf16'),
+    each input vector rounded to FP32, products summed in FP32, each power
+    stored as FP64 (the stored value is the FP32 sum, exactly)."""
+    code = {"f32": 1, "bf16": 2}[vdtype]
+    rowptr, col, val = _arrs(A)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    k = 1 if x.ndim == 1 else x.shape[1]
+    y = np.empty((p, A.n * k), dtype=np.float64)
+    rc = _load().orc_spmv_powers_lowp(A.n, _p(rowptr, _i64p), _p(col, _i32p), _p(val, _f64p),
+                                      code, k, p, _p(x, _f64p), _p(y, _f64p))
+    if rc != 0:
+        raise ValueError("orc_spmv_powers_lowp failed")
+    return y.reshape((p, A.n) if x.ndim == 1 else (p, A.n, k))
+
+
+# ----------------------------------------------------------------------------
+# levels, groups, schedule
+# ----------------------------------------------------------------------------
+
+def bfs_distances(A, root: int) -> np.ndarray:
+    """Unweighted graph distance from ``root`` in the graph of A + A^T
+    (-1 outside root's component)."""
+    rowptr, col, _ = _arrs(A)
+    d = np.empty(A.n, dtype=np.int64)
+    if _load().orc_bfs_distances(A.n, _p(rowptr, _i64p), _p(col, _i32p), int(root), _p(d, _i64p)):
+        raise ValueError("bad root")
+    return d
+
+
+def peripheral_root(A, start: int = 0) -> int:
+    """George-Liu pseudo-peripheral vertex reached from ``start``."""
+    rowptr, col, _ = _arrs(A)
+    r = _load().orc_peripheral_root(A.n, _p(rowptr, _i64p), _p(col, _i32p), int(start))
+    if r < 0:
+        raise ValueError("peripheral_root failed")
+    return int(r)
+
+
+def bfs_levels(A, root_mode: int = 0):
+    """BFS levels (Eq. 3) and the renumbering of Sec. 4.1.
+
+    root_mode 0: v_root = 0 (the choice of the worked example in Sec. 4.1);
+    root_mode 1: the pseudo-peripheral vertex reached from vertex 0.
+    Returns (perm, level_ptr): perm[new] = old (int32), level_ptr int64[L+1].
+    """
+    rowptr, col, _ = _arrs(A)
+    n = A.n
+    if n == 0:
+        return np.zeros(0, np.int32), np.zeros(1, np.int64)
+    root = 0 if root_mode == 0 else peripheral_root(A, 0)
+    perm = np.empty(n, dtype=np.int32)
+    lp = np.empty(n + 1, dtype=np.int64)
+    L = _load().orc_bfs_levels(n, _p(rowptr, _i64p), _p(col, _i32p), root,
+                               _p(perm, _i32p), _p(lp, _i64p))
+    if L < 0:
+        raise ValueError("orc_bfs_levels failed")
+    return perm, lp[: L + 1].copy()
+
+
+def level_nnz(A, perm, level_ptr) -> np.ndarray:
+    """Stored nonzeros of A in the rows of each level (int64)."""
+    rowlen = np.diff(np.asarray(A.rowptr, dtype=np.int64))
+    out = np.zeros(len(level_ptr) - 1, dtype=np.int64)
+    for i in range(len(level_ptr) - 1):
+        rows = np.asarray(perm[level_ptr[i]:level_ptr[i + 1]], dtype=np.int64)
+        out[i] = int(rowlen[rows].sum())
+    return out
+
+
+def level_groups(lnnz, p: int, cache_bytes: int, f: float = 0.5,
+                 bytes_per_nnz: int = 12) -> np.ndarray:
+    """Greedy level groups, Eq. (5): (p+1) * N_nz(T) * b < f*C.
+
+    Starting from the first ungrouped level, levels are added while the
+    accumulated group still satisfies Eq. (5) with strict '<'; a level that
+    violates Eq. (5) on its own becomes a group of its own.  The budget f*C is
+    taken as floor(f*C) bytes and every comparison is in integers.  Returns
+    group_ptr (int64[G+1], indices into the level list).
+    """
+    budget = int(np.floor(float(f) * float(cache_bytes)))
+    L = len(lnnz)
+    gptr = [0]
+    i = 0
+    while i < L:
+        acc = int(lnnz[i])
+        j = i + 1
+        while j < L and (p + 1) * (acc + int(lnnz[j])) * bytes_per_nnz < budget:
+            acc += int(lnnz[j])
+            j += 1
+        gptr.append(j)
+        i = j
+    return np.asarray(gptr, dtype=np.int64)
+
+
+def lp_schedule(G: int, p: int) -> np.ndarray:
+    """Diagonal traversal of the Lp diagram (Sec. 4.2, Fig. 6).
+
+    Diagonals d = i + p' run left to right (d = 1 .. G+p-1); inside one
+    diagonal the power p' rises from max(1, d-(G-1)) to min(d, p) and the
+    node is (i = d - p', p').  Returns int64[G*p, 3] rows (d, p', i); the row
+    index is the execution step, counted from 0.
+    """
+    out = []
+    for d in range(1, G + p):
+        for q in range(max(1, d - (G - 1)), min(d, p) + 1):
+            out.append((d, q, d - q))
+    return np.asarray(out, dtype=np.int64).reshape(-1, 3)
+
+
+def permute_symmetric(A, perm):
+    """P A P^T with perm[new] = old, columns ascending in the new numbering."""
+    n = A.n
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[np.asarray(perm, dtype=np.int64)] = np.arange(n)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for r in range(n):
+        o = int(perm[r])
+        a, b = int(A.rowptr[o]), int(A.rowptr[o + 1])
+        c = iperm[A.col[a:b].astype(np.int64)]
+        order = np.argsort(c, kind="stable")
+        cols.append(c[order])
+        vals.append(A.val[a:b][order])
+        rowptr[r + 1] = rowptr[r] + (b - a)
+    col = np.concatenate(cols).astype(np.int32) if n else np.zeros(0, np.int32)
+    val = np.concatenate(vals) if n else np.zeros(0)
+    return rowptr, col, val
+
+
+# ----------------------------------------------------------------------------
+# Chebyshev time propagation (Sec. 7)
+# ----------------------------------------------------------------------------
+
+def cheb_coefficients(M: int, r_dt: float, c_dt: float = 0.0) -> np.ndarray:
+    """c_k, k = 0..M, of exp(-i H dt) = sum_k c_k T_k(A) for H = r A + c.
+
+    Jacobi-Anger: exp(-i tau A) = J_0(tau) + 2 sum_{k>=1} (-i)^k J_k(tau) T_k(A),
+    times the phase exp(-i c dt).  J_k comes from scipy.special.jv.
+    """
+    from scipy.special import jv
+
+    k = np.arange(M + 1)
+    c = (2.0 - (k == 0)) * ((-1j) ** k) * jv(k, r_dt)
+    return c * np.exp(-1j * c_dt)
+
+
+def cheb_propagate(A, x, coeffs) -> np.ndarray:
+    """One time step x' = sum_k c_k v_k with v_0 = x, v_1 = A x,
+    v_{k+1} = 2 A v_k - v_{k-1} (Eq. 7-8).
+
+    ``x`` is complex, given as (n, 2) [re, im]; A is real, so each product is
+    an SpMV on the two real columns.  Returns (n, 2)."""
+    xc = np.asarray(x, dtype=np.float64)
+    M = len(coeffs) - 1
+    v_prev = xc.copy()
+    acc = coeffs[0].real * v_prev + coeffs[0].imag * np.stack([-v_prev[:, 1], v_prev[:, 0]], 1)
+    if M == 0:
+        return acc
+    v = spmv_powers(A, v_prev, 1)[0]
+    acc += coeffs[1].real * v + coeffs[1].imag * np.stack([-v[:, 1], v[:, 0]], 1)
+    for k in range(2, M + 1):
+        av = spmv_powers(A, v, 1)[0]
+        v_next = 2.0 * av - v_prev
+        acc += coeffs[k].real * v_next + coeffs[k].imag * np.stack([-v_next[:, 1], v_next[:, 0]], 1)
+        v_prev, v = v, v_next
+    return acc

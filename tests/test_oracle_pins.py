@@ -1,0 +1,433 @@
+"""Pins for the CPU oracle: each check ties the oracle to something other
+than itself -- values the paper prints for its worked example, closed forms,
+graph invariants, exact integer arithmetic, dense brute force and independent
+library routines.  No GPU is needed."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import oracle as O
+import workloads as W
+from conftest import read_golden
+
+
+# ----------------------------------------------------------------------------
+# levels (Eq. 3, Sec. 4.1)
+# ----------------------------------------------------------------------------
+
+def test_worked_example_levels():
+    g = read_golden("worked_example_2d7pt_8x8.txt")
+    A = W.stencil_2d(8, 7)
+    perm, lp = O.bfs_levels(A, root_mode=0)
+    assert len(lp) - 1 == int(g["n_levels"][0][0])
+    assert lp.tolist() == [int(v) for v in g["level_ptr"][0]]
+    lo, hi = (int(v) for v in g["level6"][0])
+    assert (lp[6], lp[7] - 1) == (lo, hi)
+    lo, hi = (int(v) for v in g["levels_5_to_7"][0])
+    assert (lp[5], lp[8] - 1) == (lo, hi)
+    # the renumbering is a bijection and the root comes first
+    assert sorted(perm.tolist()) == list(range(64)) and perm[0] == 0
+
+
+def test_stencil_orientation_matters():
+    # with the main-diagonal pair (x+1, y+1), (x-1, y-1) instead of the
+    # anti-diagonal pair, the 8x8 grid has Chebyshev-distance levels: 8 of
+    # them, not the 15 of Fig. 4, so the example fixes the orientation.
+    n = 8
+    v = np.arange(n * n)
+    x, y = v % n, v // n
+    dx = x[None, :] - x[:, None]
+    dy = y[None, :] - y[:, None]
+    pat = ((np.abs(dx) + np.abs(dy) <= 1) | ((dx == dy) & (np.abs(dx) == 1)))
+    M = sp.csr_matrix(pat.astype(float))
+    Ac = W.CSR(n * n, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data)
+    assert Ac.nnz == W.stencil_2d(8, 7).nnz
+    _, lp = O.bfs_levels(Ac, 0)
+    assert len(lp) - 1 == 8
+
+
+def test_levels_closed_form_2d5pt():
+    n = 64
+    A = W.stencil_2d(n, 5)
+    perm, lp = O.bfs_levels(A, 0)
+    assert len(lp) - 1 == 2 * n - 1
+    lev = np.empty(n * n, np.int64)
+    for i in range(len(lp) - 1):
+        lev[perm[lp[i]:lp[i + 1]]] = i
+    v = np.arange(n * n)
+    assert np.array_equal(lev, (v % n) + (v // n))
+
+
+@pytest.mark.parametrize("n", [6, 13])
+def test_levels_closed_form_27pt_corner(n):
+    # 27-point stencil, random relabelling: the pseudo-peripheral root is a
+    # corner and the levels are the shells max(x, y, z) = i of 3i^2+3i+1 points
+    A, new2old = W.stencil_27pt_random(n, seed=3)
+    perm, lp = O.bfs_levels(A, root_mode=1)
+    assert len(lp) - 1 == n
+    widths = np.diff(lp)
+    i = np.arange(n)
+    assert np.array_equal(widths, 3 * i * i + 3 * i + 1)
+    g = new2old[perm.astype(np.int64)]  # natural grid index of each new row
+    x, y, z = g % n, (g // n) % n, g // (n * n)
+    root = (x[0], y[0], z[0])
+    assert all(c in (0, n - 1) for c in root)
+    cheb = np.maximum(np.maximum(np.abs(x - root[0]), np.abs(y - root[1])), np.abs(z - root[2]))
+    lev = np.repeat(np.arange(n), widths)
+    assert np.array_equal(cheb, lev)
+
+
+def test_levels_closed_form_3d7pt():
+    n = 9
+    A = W.stencil_3d(n, 7)
+    perm, lp = O.bfs_levels(A, 0)
+    assert len(lp) - 1 == 3 * n - 2
+    lev = np.repeat(np.arange(len(lp) - 1), np.diff(lp))
+    g = perm.astype(np.int64)
+    assert np.array_equal(lev, g % n + (g // n) % n + g // (n * n))
+
+
+def _random_graphs():
+    rng = np.random.default_rng(11)
+    cases = []
+    for n, dens, sym in [(1, 0.0, True), (2, 0.0, True), (7, 0.3, False), (40, 0.05, False),
+                         (60, 0.02, True), (200, 0.01, False), (300, 0.004, True)]:
+        cases.append(W.random_small_csr(n, dens, rng, symmetric_pattern=sym,
+                                        empty_rows=0.05, duplicates=0.1))
+    return cases
+
+
+@pytest.mark.parametrize("A", _random_graphs())
+@pytest.mark.parametrize("root_mode", [0, 1])
+def test_levels_are_graph_distances(A, root_mode):
+    perm, lp = O.bfs_levels(A, root_mode)
+    n = A.n
+    assert sorted(perm.tolist()) == list(range(n))
+    assert np.all(np.diff(lp) > 0) and lp[0] == 0 and lp[-1] == n
+    lev = np.empty(n, np.int64)
+    lev[perm] = np.repeat(np.arange(len(lp) - 1), np.diff(lp))
+    # scipy distances on the symmetrised pattern, independent of the oracle
+    M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(n, n))
+    S = ((M + M.T) > 0).astype(float)
+    S.setdiag(0)
+    S.eliminate_zeros()
+    root = perm[0]
+    dist = shortest_path(S, unweighted=True, indices=[root])[0]
+    comp = np.isfinite(dist)
+    assert np.array_equal(lev[comp], dist[comp].astype(np.int64))
+    # Eq. (4): every stored nonzero joins equal or adjacent levels
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    assert np.all(np.abs(lev[rows] - lev[A.col]) <= 1)
+    # a level whose vertices have no neighbour in the level before starts a
+    # new component: it is one vertex, the smallest index not yet numbered
+    Sc = S.tocsr()
+    for i in range(1, len(lp) - 1):
+        lvl = perm[lp[i]:lp[i + 1]]
+        prev = set(perm[lp[i - 1]:lp[i]].tolist())
+        linked = any(int(u) in prev for v in lvl for u in Sc.indices[Sc.indptr[v]:Sc.indptr[v + 1]])
+        if not linked:
+            assert len(lvl) == 1 and lvl[0] == perm[lp[i]:].min()
+
+
+def test_within_level_order_is_discovery_order():
+    rng = np.random.default_rng(5)
+    A = W.random_small_csr(120, 0.03, rng, symmetric_pattern=True)
+    perm, lp = O.bfs_levels(A, 0)
+    n = A.n
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    nb = [set() for _ in range(n)]
+    for r in range(n):
+        for c in A.col[A.rowptr[r]:A.rowptr[r + 1]]:
+            if c != r:
+                nb[r].add(int(c))
+                nb[int(c)].add(r)
+    for i in range(1, len(lp) - 1):
+        prev = set(perm[lp[i - 1]:lp[i]].tolist())
+        lvl = perm[lp[i]:lp[i + 1]].tolist()
+        keys = []
+        for v in lvl:
+            ks = [pos[u] for u in nb[v] if u in prev]
+            keys.append((min(ks) if ks else -1, v))
+        if all(k[0] >= 0 for k in keys):
+            assert keys == sorted(keys)
+
+
+def test_peripheral_root_path_graph():
+    n = 11
+    r = np.arange(n - 1)
+    M = sp.coo_matrix((np.ones(n - 1), (r, r + 1)), shape=(n, n)).tocsr()
+    M = (M + M.T).tocsr()
+    A = W.CSR(n, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data)
+    root = O.peripheral_root(A, 5)
+    assert root in (0, n - 1)
+
+
+# ----------------------------------------------------------------------------
+# level groups (Eq. 5) and the Lp schedule (Fig. 6)
+# ----------------------------------------------------------------------------
+
+def test_group_example_six_vertex_cache():
+    g = read_golden("level_groups_6vertex_cache.txt")
+    sizes = np.array([1, 2, 3, 4, 5, 6, 7, 8, 7, 6, 5, 4, 3, 2, 1])
+    # "at most six vertices": (p+1) * N * 12 < f*C with p = 1, f*C = 150
+    gptr = O.level_groups(sizes, p=1, cache_bytes=300, f=0.5, bytes_per_nnz=12)
+    groups = []
+    for a, b in zip(gptr[:-1], gptr[1:]):
+        groups.append(f"{a}-{b - 1}" if b - a > 1 else f"{a}")
+    assert groups == g["groups"][0]
+    viol = [i for i, (a, b) in enumerate(zip(gptr[:-1], gptr[1:])) if sizes[a:b].sum() > 6]
+    assert viol == [int(v) for v in g["violators"][0]]
+
+
+@pytest.mark.parametrize("p,C,f,b", [(1, 10_000, 0.5, 12), (4, 50_000, 0.5, 12),
+                                     (8, 123_457, 0.37, 6), (2, 1, 0.5, 12)])
+def test_group_invariants(p, C, f, b):
+    rng = np.random.default_rng(p)
+    lnnz = rng.integers(1, 400, size=57)
+    gptr = O.level_groups(lnnz, p, C, f, b)
+    budget = int(np.floor(f * C))
+    assert gptr[0] == 0 and gptr[-1] == len(lnnz) and np.all(np.diff(gptr) >= 1)
+    for a, bb in zip(gptr[:-1], gptr[1:]):
+        tot = int(lnnz[a:bb].sum())
+        ok = (p + 1) * tot * b < budget
+        assert ok or bb - a == 1
+        if bb < len(lnnz) and ok:
+            assert not ((p + 1) * (tot + int(lnnz[bb])) * b < budget)
+
+
+def test_schedule_worked_example():
+    g = read_golden("lp_schedule_15x5.txt")
+    s = O.lp_schedule(15, 5)
+    assert len(s) == int(g["n_nodes"][0][0])
+    step = {(int(i), int(q)): k for k, (d, q, i) in enumerate(s)}
+    for i, q, k in g["step_of"]:
+        assert step[(int(i), int(q))] == int(k)
+    d, n = (int(v) for v in g["diag_size"][0])
+    assert (s[:, 0] == d).sum() == n
+    # steady-state reuse distance
+    rd = int(g["reuse_distance"][0][0])
+    assert step[(7, 3)] - step[(7, 2)] == rd
+    # every node exactly once, and each node comes after its three
+    # dependencies (i-1, p-1), (i, p-1), (i+1, p-1)
+    assert len(step) == 75
+    for (i, q), k in step.items():
+        if q == 1:
+            continue
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < 15:
+                assert step[(j, q - 1)] < k
+
+
+@pytest.mark.parametrize("G,p", [(1, 1), (1, 6), (3, 8), (20, 4), (9, 9)])
+def test_schedule_topological(G, p):
+    s = O.lp_schedule(G, p)
+    assert len(s) == G * p
+    step = {(int(i), int(q)): k for k, (d, q, i) in enumerate(s)}
+    assert len(step) == G * p
+    for (i, q), k in step.items():
+        for j in (i - 1, i, i + 1):
+            if q > 1 and 0 <= j < G:
+                assert step[(j, q - 1)] < k
+
+
+# ----------------------------------------------------------------------------
+# powers (Sec. 3.1)
+# ----------------------------------------------------------------------------
+
+def test_powers_2d5pt_eigenvectors():
+    n = 64
+    A = W.stencil_2d(n, 5)
+    v = np.arange(n * n)
+    x, y = v % n, v // n
+    for (j, k) in [(1, 1), (3, 7), (64, 2)]:
+        e = np.sin(j * np.pi * (x + 1) / (n + 1)) * np.sin(k * np.pi * (y + 1) / (n + 1))
+        lam = 4 - 2 * np.cos(j * np.pi / (n + 1)) - 2 * np.cos(k * np.pi / (n + 1))
+        Y = O.spmv_powers(A, e, 4)
+        # rounding scale: |A|^p |e| (8^p |e| here); a dropped term or a wrong
+        # sign would leave an O(1) relative error against it
+        for p in range(1, 5):
+            scale = 8.0 ** p * np.linalg.norm(e)
+            assert np.linalg.norm(Y[p - 1] - lam ** p * e) <= 50 * p * 2.0 ** -52 * scale
+            assert np.linalg.norm(Y[p - 1] - lam ** p * e) <= 1e-12 * max(lam ** p, 1.0) * np.linalg.norm(e) * 8 ** p
+
+
+def test_powers_27pt_eigenvectors_permuted():
+    n = 12
+    A = W.stencil_3d(n, 27)
+    rng = np.random.default_rng(0)
+    new2old = rng.permutation(n ** 3)
+    B = W.relabel(A, new2old)
+    g = new2old
+    x, y, z = g % n, (g // n) % n, g // (n * n)
+    j = (2, 5, 11)
+    e = (np.sin(j[0] * np.pi * (x + 1) / (n + 1)) * np.sin(j[1] * np.pi * (y + 1) / (n + 1))
+         * np.sin(j[2] * np.pi * (z + 1) / (n + 1)))
+    lam = 27 - np.prod([1 + 2 * np.cos(jj * np.pi / (n + 1)) for jj in j])
+    Y = O.spmv_powers(B, e, 6)
+    for p in range(1, 7):
+        err = np.linalg.norm(Y[p - 1] - lam ** p * e) / np.linalg.norm(lam ** p * e)
+        assert err < 1e-12
+
+
+def test_powers_integer_exact():
+    n = 6
+    A = W.integer_stencil_27pt(n, seed=4)
+    rng = np.random.default_rng(1)
+    x = rng.integers(-1, 2, size=A.n).astype(np.float64)
+    Y = O.spmv_powers(A, x, 8)
+    D = A.to_dense().astype(np.int64)
+    xi = x.astype(np.int64)
+    for p in range(8):
+        xi = D @ xi
+        assert np.array_equal(Y[p], xi.astype(np.float64))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_powers_dense_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    A = W.random_small_csr(150 + 50 * seed, 0.04, rng, empty_rows=0.1, duplicates=0.2)
+    D = A.to_dense()
+    x = rng.uniform(-1, 1, size=(A.n, 3))
+    Y = O.spmv_powers(A, x, 5)
+    for p in range(1, 6):
+        ref = np.linalg.matrix_power(D, p) @ x
+        assert np.allclose(Y[p - 1], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_powers_vs_scipy():
+    A, _ = W.stencil_27pt_random(10, seed=9)
+    M = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    x = W.uniform_vector(A.n, seed=9)
+    Y = O.spmv_powers(A, x, 4)
+    v = x
+    for p in range(4):
+        v = M @ v
+        assert np.allclose(Y[p], v, rtol=1e-13, atol=0)
+
+
+def test_powers_row_stochastic():
+    A, _ = W.random_geometric(3000, 10.0, seed=2)
+    assert np.allclose(np.bincount(np.repeat(np.arange(A.n), np.diff(A.rowptr)), A.val), 1.0)
+    Y = O.spmv_powers(A, np.ones(A.n), 6)
+    assert np.allclose(Y, 1.0, rtol=0, atol=1e-13)
+
+
+def test_powers_empty_and_single():
+    A = W.CSR(1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([3.0]))
+    Y = O.spmv_powers(A, np.array([2.0]), 3)
+    assert Y.ravel().tolist() == [6.0, 18.0, 54.0]
+    Z = W.CSR(3, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert np.all(O.spmv_powers(Z, np.ones(3), 2) == 0)
+
+
+# ----------------------------------------------------------------------------
+# mixed precision definition
+# ----------------------------------------------------------------------------
+
+def test_lowp_exact_on_representable_integers():
+    # entries in {-2..2} are exact in bf16 and f32; |A^4 x| < 2^24, so every
+    # FP32 partial sum is exact and the low-precision powers equal FP64 ones
+    A = W.integer_stencil_27pt(5, seed=8)
+    rng = np.random.default_rng(3)
+    x = rng.integers(-1, 2, size=A.n).astype(np.float64)
+    ref = O.spmv_powers(A, x, 4)
+    for dt in ("f32", "bf16"):
+        assert np.array_equal(O.spmv_powers_lowp(A, x, 4, dt), ref)
+
+
+def test_lowp_rounding_rules():
+    # bf16 keeps 8 significant bits: 1 + 2^-8 is a tie and rounds to even (1);
+    # 1 + 3*2^-8 rounds up to 1 + 2^-6; f32 rounds 1 + 2^-30 to 1
+    vals = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -30])
+    A = W.CSR(3, np.arange(4, dtype=np.int64), np.arange(3, dtype=np.int32), vals)
+    yb = O.spmv_powers_lowp(A, np.ones(3), 1, "bf16")[0]
+    yf = O.spmv_powers_lowp(A, np.ones(3), 1, "f32")[0]
+    assert yb.tolist() == [1.0, 1 + 2.0 ** -6, 1.0]
+    assert yf.tolist() == [float(np.float32(1 + 2.0 ** -8)), float(np.float32(1 + 3 * 2.0 ** -8)), 1.0]
+
+
+def test_lowp_error_within_bound():
+    A, _ = W.stencil_27pt_random(8, seed=1)
+    x = W.uniform_vector(A.n, seed=1)
+    ref = O.spmv_powers(A, x, 3)
+    absA = W.CSR(A.n, A.rowptr, A.col, np.abs(A.val))
+    for dt, u in (("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        y = O.spmv_powers_lowp(A, x, 3, dt)
+        bound = O.spmv_powers(absA, np.abs(x), 3)
+        for p in range(3):
+            # first-order bound: each power adds <= (u_val + (nrow+1) 2^-24) |A||y|
+            c = (p + 1) * (u + 30 * 2.0 ** -24) * 1.01
+            assert np.all(np.abs(y[p] - ref[p]) <= c * bound[p] + 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# Chebyshev (Sec. 7)
+# ----------------------------------------------------------------------------
+
+def test_cheb_coefficients_scalar_identity():
+    tau = 10.0
+    c = O.cheb_coefficients(40, tau)
+    th = np.linspace(0, np.pi, 17)
+    T = np.cos(np.outer(np.arange(41), th))
+    approx = (c[:, None] * T).sum(0)
+    assert np.allclose(approx, np.exp(-1j * tau * np.cos(th)), atol=1e-12)
+
+
+def test_cheb_propagate_vs_expm():
+    from scipy.linalg import expm
+    A = W.anderson_3d(6, seed=2)
+    D = A.to_dense()
+    x = W.random_phase_state(A.n, seed=2)
+    tau = 10.0
+    c = O.cheb_coefficients(40, tau)
+    out = O.cheb_propagate(A, x, c)
+    ref = expm(-1j * tau * D) @ (x[:, 0] + 1j * x[:, 1])
+    assert np.allclose(out[:, 0] + 1j * out[:, 1], ref, atol=1e-11)
+    assert abs(np.linalg.norm(out) - 1.0) < 1e-11
+
+
+def test_cheb_truncation_tail():
+    # degree 32 at r*dt = 10: every dropped |c_k| is below 1e-4 (the paper's
+    # cut-off) and the truncated propagator stays unitary to ~1e-12
+    from scipy.special import jv
+    assert 2 * abs(jv(32, 10.0)) < 1e-12
+    A = W.anderson_3d(5, seed=1)
+    x = W.random_phase_state(A.n, seed=1)
+    out = O.cheb_propagate(A, x, O.cheb_coefficients(32, 10.0))
+    assert abs(np.linalg.norm(out) - 1.0) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# generators (nonzero counts printed in Tables 2 and 3)
+# ----------------------------------------------------------------------------
+
+def _star_nnz(n, r):
+    return n ** 3 * (6 * r + 1) - 6 * n * n * sum(range(1, r + 1))
+
+
+def test_generator_counts_small():
+    for n in (3, 5, 8):
+        assert W.stencil_3d(n, 27).nnz == (3 * n - 2) ** 3
+        for order, pts in ((2, 7), (4, 13), (6, 19)):
+            assert W.star_stencil_3d(n, order).nnz == _star_nnz(n, order // 2)
+    assert W.stencil_2d(64, 5).nnz == 20224
+
+
+def test_generator_counts_paper_tables():
+    assert (3 * 128 - 2) ** 3 == 55_742_968           # HPCG 128^3, Table 2
+    assert _star_nnz(160, 1) == 28_518_400             # order-2, Table 3
+    assert _star_nnz(160, 2) == 52_787_200             # order-4, Table 3
+    assert _star_nnz(160, 3) == 76_902_400             # order-6, Table 3
+    assert _star_nnz(200, 1) == 55_760_000             # Anderson 200^3, Table 3
+    # the formula matches the generator where generation is cheap
+    assert W.anderson_3d(7).nnz == _star_nnz(7, 1)
+
+
+def test_rgg_shape():
+    A, _ = W.random_geometric(20000, 16.0, seed=0)
+    deg = np.diff(A.rowptr)
+    assert 13.0 < deg.mean() < 17.0
+    M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
+    assert (M != M.T).nnz == 0
