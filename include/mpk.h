@@ -1,0 +1,232 @@
+/*
+ * mpk.h -- C-ABI of the level-blocked sparse matrix power kernel (MPK) for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method follows "Level-based Blocking for Sparse Matrices: Sparse
+ * Matrix-Power-Vector Multiplication" (Alappat, Hager, Schenk, Wellein,
+ * arXiv 2205.01598):
+ *   - the MPK computes y_p = A^p x for p = 1..p_m and keeps every y_p
+ *     (Sec. 3);
+ *   - preprocessing takes A, p_m and a cache budget C, levels the graph of A
+ *     by breadth-first search (Eq. 3), renumbers it level by level (Sec. 4.1),
+ *     merges consecutive levels into level groups under Eq. (5) (Sec. 4.3)
+ *     and orders the (group, power) nodes by the diagonals of the Lp diagram
+ *     (Sec. 4.2, Fig. 6);
+ *   - execution runs the powers over that order with point-to-point
+ *     dependencies instead of barriers (Sec. 4.3, "p2p").
+ * The baseline is p_m back-to-back SpMVs (Sec. 3.1, Fig. 2).
+ *
+ * Conventions for every entry point
+ *   - All calls return mpk_status (0 = MPK_OK, < 0 = error).  No call aborts
+ *     the process; on error nothing is written to caller outputs unless the
+ *     entry point says otherwise, and mpk_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - "host" pointers point to CPU memory, "device" pointers to memory on the
+ *     GPU that is current when the call is made (hipMalloc / torch tensors).
+ *   - Streams are passed as `void *` holding a hipStream_t (NULL = the null
+ *     stream).  Device work is asynchronous on that stream.
+ *   - Vectors are FP64, row-major N x k (k right-hand sides; element (i, c)
+ *     at index i*k + c).  Power blocks are p x N x k: y_q occupies
+ *     [(q-1)*N*k, q*N*k).
+ *   - Plans and SpMV handles are not thread-safe; one run per plan may be in
+ *     flight at a time (its dependency flags live in the plan).
+ */
+#ifndef MPK_H_
+#define MPK_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPK_MAX_POWER 32
+#define MPK_MAX_NRHS 32
+
+typedef int32_t mpk_status;
+enum {
+    MPK_OK = 0,
+    MPK_ERR_ARG = -1,          /* bad argument (null pointer, p out of range, ...) */
+    MPK_ERR_CSR = -2,          /* malformed CSR: rowptr not monotone, column out of range, ... */
+    MPK_ERR_OOM = -3,          /* host or device allocation failed */
+    MPK_ERR_HIP = -4,          /* a HIP runtime call failed */
+    MPK_ERR_TIMEOUT = -5,      /* a device dependency wait exceeded the watchdog */
+    MPK_ERR_UNSUPPORTED = -6,  /* valid request this build does not handle (e.g. nnz >= 2^31) */
+    MPK_ERR_STATE = -7         /* call out of order (e.g. run before upload) */
+};
+
+typedef enum { MPK_F64 = 0, MPK_F32 = 1, MPK_BF16 = 2 } mpk_dtype;
+
+/* Host CSR matrix, 0-based, square (n x n).  rowptr[n+1] (int64, monotone,
+ * rowptr[0] = 0, rowptr[n] = nnz), col[nnz] (int32 in [0, n)), val[nnz].
+ * Duplicate (row, col) entries are allowed and are summed like any other
+ * stored entry; empty rows are allowed.  Column order inside a row is free. */
+typedef struct mpk_csr {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} mpk_csr;
+
+/* Options.  Call mpk_options_default() first, then change fields. */
+typedef struct mpk_options {
+    uint32_t size;            /* sizeof(mpk_options), for ABI growth */
+    double safety_factor;     /* f of Eq. (5); default 0.5 as in Sec. 4.3 */
+    int32_t root_mode;        /* BFS root: 0 = vertex 0 (Sec. 4.1 example), 1 = pseudo-peripheral */
+    int32_t val_dtype;        /* mpk_dtype of stored matrix values (default MPK_F64) */
+    int32_t nrhs;             /* k, right-hand sides per run, 1..MPK_MAX_NRHS (default 1) */
+    int32_t workgroups;       /* persistent-kernel grid size; 0 = automatic */
+    int32_t tile_nnz;         /* target nonzeros per device tile; 0 = automatic */
+    int32_t lanes_per_row;    /* lanes cooperating on one row: 4..64 (power of 2, >= k); 0 = auto */
+    int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
+    int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
+                                 ((p+1)(b_nz nnz + 8 k rows) < fC); 0 = the paper's form */
+    int32_t reserved[7];
+} mpk_options;
+
+/* Plan summary (mpk_plan_query). */
+typedef struct mpk_plan_info {
+    int64_t n, nnz;
+    int32_t p;                /* p_m */
+    int32_t nrhs;
+    int64_t n_levels;         /* L */
+    int64_t n_groups;         /* G */
+    int64_t n_tiles;          /* device tiles (row ranges inside groups) */
+    int64_t n_tickets;        /* n_tiles * p: work items of one run */
+    int64_t root;             /* BFS root (original index) */
+    int64_t max_level_rows, max_group_nnz;
+    int64_t violating_groups; /* groups that break Eq. (5) (single bulky levels) */
+    uint64_t device_bytes;    /* device memory held after mpk_plan_upload */
+    int32_t workgroups;       /* grid size mpk_run will launch */
+    int32_t lanes_per_row;
+    int32_t tile_nnz;
+    int32_t val_dtype;
+    double plan_seconds;      /* host time spent in mpk_plan_create */
+} mpk_plan_info;
+
+/* Three-term recurrence epilogue for mpk_run / mpk_run_baseline (Sec. 7,
+ * Eq. (7)-(8)).  For q = 1..p the kernel computes
+ *     y_q = alpha[q-1] * (A y_{q-1}) + beta[q-1] * y_{q-1} + gamma[q-1] * y_{q-2}
+ * with y_0 = X and y_{-1} = y_prev (device, N x k; may be NULL when every
+ * gamma is 0), and, when acc != NULL,
+ *     acc += coef_q * y_q
+ * where coef is real (coef[q-1]) or, with complex_pairs = 1, complex
+ * (coef[2(q-1)] + i coef[2(q-1)+1]) acting on k = 2 columns holding
+ * (re, im) of one complex vector.  Coefficient arrays are host memory with p
+ * (or 2p) entries, copied into the launch; y_prev and acc are device memory.
+ * Chebyshev: alpha = (1, 2, 2, ...), beta = 0, gamma = (0, -1, -1, ...) in
+ * the first block; later blocks pass the last two vectors of the previous
+ * block as y_prev and X and use alpha = 2, gamma = -1 throughout. */
+typedef struct mpk_recurrence {
+    const double *alpha;
+    const double *beta;
+    const double *gamma;
+    const double *coef;
+    int32_t complex_pairs;
+    const double *y_prev;
+    double *acc;
+} mpk_recurrence;
+
+typedef struct mpk_plan mpk_plan;
+typedef struct mpk_spmv mpk_spmv;
+
+/* Fill *opt with defaults (f = 0.5, root_mode 0, F64, k = 1, automatic launch). */
+void mpk_options_default(mpk_options *opt);
+
+/* Preprocessing (Sec. 4, "RACE" paragraph): validate A, build the graph of
+ * A + A^T (diagonal dropped; Sec. 4 notes non-symmetric A is allowed), BFS
+ * levels from the root (Eq. 3), level-by-level renumbering (Sec. 4.1), level
+ * groups under Eq. (5) with budget floor(f*C) bytes and b_nz = sizeof(value)+4
+ * bytes per nonzero (12 for FP64, Sec. 3.1), the Lp diagonal order of the
+ * groups (Fig. 6), and device tiles with their point-to-point dependency
+ * ranges (Sec. 4.3).  Host work only: no GPU call is made.  The CSR is
+ * copied; the caller may free it on return.  p in [1, MPK_MAX_POWER],
+ * cache_bytes > 0.  *out receives a new plan (free with mpk_plan_destroy).
+ * Errors: MPK_ERR_ARG, MPK_ERR_CSR, MPK_ERR_OOM, MPK_ERR_UNSUPPORTED
+ * (nnz >= 2^31 or n >= 2^31). */
+mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
+                           const mpk_options *opt, mpk_plan **out);
+
+/* Summary of a plan.  info: host, written on success. */
+mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info);
+
+/* Host copies of the plan arrays.  Any pointer may be NULL to skip it.
+ *   perm[n]        perm[new] = old (the permutation vector of Sec. 4.1)
+ *   level_ptr[L+1] first new row of each level (Fig. 4e)
+ *   group_ptr[G+1] first level of each level group (Sec. 4.3)
+ *   schedule[3*G*p] execution order of the Lp diagram: rows (d, p, i) with
+ *                  d = i + p, step = row index (Fig. 6) */
+mpk_status mpk_plan_arrays(const mpk_plan *plan, int32_t *perm, int32_t *level_ptr,
+                           int32_t *group_ptr, int32_t *schedule);
+
+/* Host copy of the renumbered matrix P A P^T (columns ascending per row),
+ * FP64 values as given (before any dtype conversion).  rowptr[n+1],
+ * col[nnz], val[nnz]; any pointer may be NULL. */
+mpk_status mpk_plan_matrix(const mpk_plan *plan, int64_t *rowptr, int32_t *col, double *val);
+
+/* Device tile table (host copies): tile_row[n_tiles+1] first row of each
+ * tile, dep_lo/dep_hi[n_tiles] the first/last tile whose power q-1 a tile
+ * waits for before computing power q, work[n_tickets] ticket order (tile *
+ * 64 + (q-1)).  Any pointer may be NULL. */
+mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_lo,
+                          int32_t *dep_hi, int32_t *work);
+
+/* Allocate the plan's device buffers on the current HIP device and copy the
+ * renumbered matrix (converted to val_dtype, round to nearest even) and the
+ * tile tables there.  Synchronous.  Errors: MPK_ERR_OOM, MPK_ERR_HIP. */
+mpk_status mpk_plan_upload(mpk_plan *plan);
+
+/* Gather/scatter between the original and the plan numbering (N x k FP64,
+ * device).  to_plan = 1: out[i] = in[perm[i]]; to_plan = 0: out[perm[i]] =
+ * in[i].  in and out must not alias. */
+mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int32_t k,
+                       int32_t to_plan, void *stream);
+
+/* One level-blocked MPK run (Sec. 4.2-4.3) in plan numbering: X (device,
+ * N x k, read only) holds y_0; Y (device, p x N x k) receives y_1..y_p.  Y
+ * must not overlap X, y_prev or acc.  rec = NULL gives plain powers.
+ * k is the plan's nrhs.  Asynchronous; a dependency wait that outlives the
+ * watchdog makes the kernel stop early and is reported by mpk_plan_status. */
+mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec,
+                   void *stream);
+
+/* Baseline on the renumbered matrix: p back-to-back SpMV launches (Fig. 2)
+ * over the plan's device matrix, same arguments and results as mpk_run. */
+mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y,
+                            const mpk_recurrence *rec, void *stream);
+
+/* Waits for `stream` and reports whether the last mpk_run on this plan hit
+ * the watchdog (MPK_ERR_TIMEOUT) or succeeded (MPK_OK). */
+mpk_status mpk_plan_status(mpk_plan *plan, void *stream);
+
+/* Release host and device memory of a plan (NULL is ignored). */
+void mpk_plan_destroy(mpk_plan *plan);
+
+/* Baseline SpMV on a matrix in its given order (Sec. 3.1, Fig. 2).  The CSR
+ * is validated, copied to the current device (values converted to
+ * opt->val_dtype) and kept by the handle.  opt may be NULL. */
+mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out);
+/* y = A x (device, N x k). */
+mpk_status spmv_run(mpk_spmv *h, const double *x, double *y, void *stream);
+/* p back-to-back SpMVs: Y[q-1] = A Y[q-2], Y[-1] = X (device). */
+mpk_status spmv_powers_run(mpk_spmv *h, int32_t p, const double *X, double *Y, void *stream);
+void spmv_destroy(mpk_spmv *h);
+
+/* Load-only bandwidth probe (the analog of the paper's Fig. 1): reads
+ * `bytes` (device, 16-byte aligned, multiple of 16) `reps` times with a grid
+ * of `workgroups` x 256 threads and returns the sum of what it read in
+ * *sink (device, one double).  Time it with events on `stream`. */
+mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups,
+                        double *sink, void *stream);
+
+const char *mpk_status_string(mpk_status s);
+const char *mpk_last_error(void);
+/* Library version string. */
+const char *mpk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPK_H_ */

@@ -1,0 +1,790 @@
+// Kernels and C-ABI of the MPK library (gfx950).
+//
+//  * spmv_kernel      one SpMV over all rows (the baseline of Sec. 3.1,
+//                     Fig. 2); p launches back to back give the baseline MPK.
+//  * mpk_persistent   the level-blocked MPK (Sec. 4.2-4.3): a persistent grid
+//                     draws tickets from one counter in the Lp diagonal order
+//                     of the level groups (Fig. 6); a ticket is one device
+//                     tile (a row range inside a level group) at one power.
+//                     Before computing power q of a tile, one wavefront polls
+//                     the "power q-1 done" flags of every tile that holds a
+//                     column the tile reads (point-to-point synchronisation,
+//                     Sec. 4.3) instead of a barrier; after the tile is
+//                     written the workgroup releases its own flag at agent
+//                     scope.  Every ticket only waits for earlier tickets, so
+//                     the grid needs no co-residency and cannot deadlock; a
+//                     bounded spin (watchdog) turns a lost flag into an error.
+//  * permute_*        gather/scatter between original and level numbering.
+//  * bw_probe         load-only bandwidth probe (the analog of Fig. 1).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mpk_internal.h"
+
+namespace mpk {
+const char *last_error_cstr();
+}
+
+using namespace mpk;
+
+// ----------------------------------------------------------------------------
+// plan / handle objects
+// ----------------------------------------------------------------------------
+
+struct mpk_plan {
+    HostPlan hp;
+    bool uploaded = false;
+    int device = -1;
+    int32_t workgroups = 0;
+    int32_t num_cus = 0;
+    uint32_t epoch = 0;
+    uint64_t device_bytes = 0;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr;
+    void *d_val = nullptr;
+    int32_t *d_tile_row = nullptr, *d_dep_lo = nullptr, *d_dep_hi = nullptr, *d_work = nullptr;
+    int32_t *d_perm = nullptr;
+    uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
+    std::vector<void *> allocs;
+};
+
+struct mpk_spmv {
+    int64_t n = 0, nnz = 0;
+    int32_t dtype = MPK_F64, nrhs = 1, lanes = 0;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr;
+    void *d_val = nullptr;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+constexpr int kCtrlWords = 16;  // [0] ticket, [1] exit count, [2] error epoch, [3] error ticket
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP,         \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+template <typename T>
+hipError_t dev_alloc(std::vector<void *> &allocs, T **p, size_t count, uint64_t *bytes = nullptr) {
+    size_t b = std::max<size_t>(sizeof(T) * count, 256);
+    hipError_t e = hipMalloc((void **)p, b);
+    if (e == hipSuccess) {
+        allocs.push_back((void *)*p);
+        if (bytes) *bytes += b;
+    }
+    return e;
+}
+
+void free_all(std::vector<void *> &allocs) {
+    for (void *p : allocs) (void)hipFree(p);
+    allocs.clear();
+}
+
+// f64 -> f32 (round to nearest even, the C conversion) -> bf16 (round to
+// nearest even on the upper 16 bits; NaN kept quiet)
+uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
+    uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + rounding) >> 16);
+}
+
+size_t value_bytes(int32_t dtype) { return dtype == MPK_F64 ? 8 : dtype == MPK_F32 ? 4 : 2; }
+
+void convert_values(const double *src, size_t n, int32_t dtype, std::vector<uint8_t> &out) {
+    out.resize(std::max<size_t>(n * value_bytes(dtype), 1));
+    if (dtype == MPK_F64) {
+        std::memcpy(out.data(), src, n * 8);
+    } else if (dtype == MPK_F32) {
+        float *o = reinterpret_cast<float *>(out.data());
+        for (size_t i = 0; i < n; ++i) o[i] = (float)src[i];
+    } else {
+        uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
+        for (size_t i = 0; i < n; ++i) o[i] = f32_to_bf16_bits((float)src[i]);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// kernels
+// ----------------------------------------------------------------------------
+
+template <typename VT, int K, int G, bool REC>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const VT *__restrict__ val, int n,
+                                                      int rows_per_block, const double *__restrict__ x,
+                                                      double *__restrict__ y, int q,
+                                                      const double *__restrict__ yq2, RecArgs rec) {
+    const int r0 = blockIdx.x * rows_per_block;
+    const int r1 = min(n, r0 + rows_per_block);
+    rows_pass<VT, K, G, REC>(r0, r1, rowptr, col, val, x, y, q, yq2, rec);
+}
+
+struct MpkArgs {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const void *val;
+    const int32_t *tile_row;
+    const int32_t *dep_lo;
+    const int32_t *dep_hi;
+    const int32_t *work;
+    int32_t n, ntiles, ntickets;
+    const double *X;
+    double *Y;
+    uint32_t *flags;
+    uint32_t *ctrl;
+    uint32_t epoch;
+    int64_t watchdog;
+};
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Executed by one full wavefront.  Waits until flags[lo..hi] all hold
+// `epoch`; returns false if the watchdog expired or another workgroup already
+// reported a timeout in this run.
+__device__ bool wait_flags(const uint32_t *f, int lo, int hi, const MpkArgs &a, int ticket) {
+    const int lane = threadIdx.x & 63;
+    int64_t spins = 0;
+    for (int base = lo; base <= hi; base += 64) {
+        const int j = base + lane;
+        for (;;) {
+            const bool ok = (j > hi) || (ld_agent(f + j) == a.epoch);
+            if (__all(ok)) break;
+            ++spins;
+            if (spins > a.watchdog) {
+                if (lane == 0) {
+                    st_agent(a.ctrl + 3, (uint32_t)ticket);
+                    st_agent(a.ctrl + 2, a.epoch);
+                }
+                return false;
+            }
+            if ((spins & 255) == 0 && ld_agent(a.ctrl + 2) == a.epoch) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+template <typename VT, int K, int G, bool REC>
+__global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec) {
+    __shared__ int s_ticket;
+    __shared__ int s_ok;
+    const int64_t NK = (int64_t)a.n * K;
+    const VT *val = reinterpret_cast<const VT *>(a.val);
+    for (;;) {
+        __syncthreads();  // everyone has read the previous ticket
+        if (threadIdx.x == 0) {
+            const uint32_t t = __hip_atomic_fetch_add(a.ctrl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool aborted = ld_agent(a.ctrl + 2) == a.epoch;
+            s_ticket = (aborted || t >= (uint32_t)a.ntickets) ? -1 : (int)t;
+            s_ok = 1;
+        }
+        __syncthreads();
+        const int t = s_ticket;
+        if (t < 0) break;
+        const int w = a.work[t];
+        const int tile = w >> 6;
+        const int q = (w & 63) + 1;
+        if (q > 1) {
+            if (threadIdx.x < 64) {
+                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep_lo[tile],
+                                           a.dep_hi[tile], a, t);
+                if (!ok && threadIdx.x == 0) s_ok = 0;
+            }
+            __syncthreads();
+            if (!s_ok) break;
+        }
+        const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
+        double *yout = a.Y + (int64_t)(q - 1) * NK;
+        const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
+        rows_pass<VT, K, G, REC>(a.tile_row[tile], a.tile_row[tile + 1], a.rowptr, a.col, val, xin, yout,
+                                 q, yq2, rec);
+        // every wavefront makes its stores visible at agent scope before the
+        // workgroup publishes the tile
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, a.epoch);
+    }
+    // the last workgroup to leave resets the counters for the next run
+    if (threadIdx.x == 0) {
+        const uint32_t done = __hip_atomic_fetch_add(a.ctrl + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            st_agent(a.ctrl + 0, 0u);
+            st_agent(a.ctrl + 1, 0u);
+        }
+    }
+}
+
+__global__ void permute_gather(const double *__restrict__ in, double *__restrict__ out,
+                               const int32_t *__restrict__ perm, int64_t n, int k) {
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / k, c = i - r * k;
+        out[i] = in[(int64_t)perm[r] * k + c];
+    }
+}
+
+__global__ void permute_scatter(const double *__restrict__ in, double *__restrict__ out,
+                                const int32_t *__restrict__ perm, int64_t n, int k) {
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / k, c = i - r * k;
+        out[(int64_t)perm[r] * k + c] = in[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void bw_probe(const double2 *__restrict__ buf, int64_t n2, int reps,
+                                                   double *sink) {
+    double acc = 0.0;
+    for (int rep = 0; rep < reps; ++rep) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const double2 v = buf[i];
+            acc += v.x + v.y;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0 && acc == 12345.678) sink[0] = acc;  // keeps the loads alive
+}
+
+// ----------------------------------------------------------------------------
+// launch dispatch: value type x columns K x lanes G x recurrence
+// ----------------------------------------------------------------------------
+
+template <typename VT, int K, bool REC>
+struct Dispatch {
+    static hipError_t spmv(int G, int blocks, int rpb, hipStream_t s, const int32_t *rp, const int32_t *ci,
+                           const void *v, int n, const double *x, double *y, int q, const double *yq2,
+                           const RecArgs &rec) {
+        const VT *val = reinterpret_cast<const VT *>(v);
+#define MPK_SPMV_CASE(GG)                                                                              \
+    case GG:                                                                                           \
+        if constexpr (GG >= K) {                                                                       \
+            hipLaunchKernelGGL((spmv_kernel<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, rp, ci, \
+                               val, n, rpb, x, y, q, yq2, rec);                                        \
+            return hipGetLastError();                                                                  \
+        }                                                                                              \
+        break;
+        switch (G) {
+            MPK_SPMV_CASE(4)
+            MPK_SPMV_CASE(8)
+            MPK_SPMV_CASE(16)
+            MPK_SPMV_CASE(32)
+            MPK_SPMV_CASE(64)
+        }
+#undef MPK_SPMV_CASE
+        return hipErrorInvalidValue;
+    }
+    static hipError_t mpk(int G, int blocks, hipStream_t s, const MpkArgs &a, const RecArgs &rec) {
+#define MPK_RUN_CASE(GG)                                                                              \
+    case GG:                                                                                          \
+        if constexpr (GG >= K) {                                                                      \
+            hipLaunchKernelGGL((mpk_persistent<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, a, rec); \
+            return hipGetLastError();                                                                 \
+        }                                                                                             \
+        break;
+        switch (G) {
+            MPK_RUN_CASE(4)
+            MPK_RUN_CASE(8)
+            MPK_RUN_CASE(16)
+            MPK_RUN_CASE(32)
+            MPK_RUN_CASE(64)
+        }
+#undef MPK_RUN_CASE
+        return hipErrorInvalidValue;
+    }
+    static const void *mpk_symbol(int G) {
+        switch (G) {
+            case 4: if constexpr (4 >= K) return (const void *)mpk_persistent<VT, K, 4, REC>; break;
+            case 8: if constexpr (8 >= K) return (const void *)mpk_persistent<VT, K, 8, REC>; break;
+            case 16: if constexpr (16 >= K) return (const void *)mpk_persistent<VT, K, 16, REC>; break;
+            case 32: return (const void *)mpk_persistent<VT, K, 32, REC>;
+            case 64: return (const void *)mpk_persistent<VT, K, 64, REC>;
+        }
+        return nullptr;
+    }
+};
+
+// What is compiled: FP64 for every K in {1,2,4,8,16,32} (recurrence for K <= 2);
+// FP32 and BF16 values for K in {1, 2} with and without the recurrence.
+template <typename VT, bool REC>
+struct ByK {
+    template <typename F>
+    static hipError_t call(int K, F &&f) {
+        switch (K) {
+            case 1: return f(Dispatch<VT, 1, REC>{});
+            case 2: return f(Dispatch<VT, 2, REC>{});
+        }
+        if constexpr (std::is_same<VT, double>::value && !REC) {
+            switch (K) {
+                case 4: return f(Dispatch<VT, 4, REC>{});
+                case 8: return f(Dispatch<VT, 8, REC>{});
+                case 16: return f(Dispatch<VT, 16, REC>{});
+                case 32: return f(Dispatch<VT, 32, REC>{});
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+};
+
+template <typename F>
+hipError_t dispatch_all(int dtype, int K, bool rec, F &&f) {
+    switch (dtype) {
+        case MPK_F64: return rec ? ByK<double, true>::call(K, f) : ByK<double, false>::call(K, f);
+        case MPK_F32: return rec ? ByK<float, true>::call(K, f) : ByK<float, false>::call(K, f);
+        case MPK_BF16: return rec ? ByK<bf16_t, true>::call(K, f) : ByK<bf16_t, false>::call(K, f);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool supported(int dtype, int K, bool rec) {
+    if (K == 1 || K == 2) return true;
+    if (K == 4 || K == 8 || K == 16 || K == 32) return dtype == MPK_F64 && !rec;
+    return false;
+}
+
+mpk_status fill_rec(const mpk_recurrence *r, int p, int K, RecArgs &out) {
+    std::memset(&out, 0, sizeof(out));
+    for (int i = 0; i < MPK_MAX_POWER; ++i) out.alpha[i] = 1.0;
+    if (!r) return MPK_OK;
+    if (r->complex_pairs && K != 2) return fail(MPK_ERR_ARG, "complex_pairs needs nrhs == 2");
+    for (int i = 0; i < p; ++i) {
+        out.alpha[i] = r->alpha ? r->alpha[i] : 1.0;
+        out.beta[i] = r->beta ? r->beta[i] : 0.0;
+        out.gamma[i] = r->gamma ? r->gamma[i] : 0.0;
+        if (r->coef) {
+            out.coef_re[i] = r->complex_pairs ? r->coef[2 * i] : r->coef[i];
+            out.coef_im[i] = r->complex_pairs ? r->coef[2 * i + 1] : 0.0;
+        }
+        if (out.gamma[i] != 0.0 && i == 0 && !r->y_prev)
+            return fail(MPK_ERR_ARG, "gamma[0] != 0 needs y_prev");
+    }
+    if (r->acc && !r->coef) return fail(MPK_ERR_ARG, "acc needs coef");
+    out.y_prev = r->y_prev;
+    out.acc = r->acc;
+    out.complex_pairs = r->complex_pairs;
+    return MPK_OK;
+}
+
+int rows_per_block_for(int G) { return (kBlock / G) * 4; }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C-ABI
+// ----------------------------------------------------------------------------
+
+extern "C" {
+
+void mpk_options_default(mpk_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->size = sizeof(mpk_options);
+    opt->safety_factor = 0.5;
+    opt->root_mode = 0;
+    opt->val_dtype = MPK_F64;
+    opt->nrhs = 1;
+    opt->watchdog_spins = 0;
+}
+
+const char *mpk_version(void) { return "mpk-gfx950 0.1"; }
+
+const char *mpk_last_error(void) { return last_error_cstr(); }
+
+const char *mpk_status_string(mpk_status s) {
+    switch (s) {
+        case MPK_OK: return "ok";
+        case MPK_ERR_ARG: return "invalid argument";
+        case MPK_ERR_CSR: return "malformed CSR matrix";
+        case MPK_ERR_OOM: return "out of memory";
+        case MPK_ERR_HIP: return "HIP runtime error";
+        case MPK_ERR_TIMEOUT: return "device dependency wait timed out";
+        case MPK_ERR_UNSUPPORTED: return "unsupported configuration";
+        case MPK_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes, const mpk_options *opt,
+                           mpk_plan **out) {
+    if (!out) return fail(MPK_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    mpk_options o;
+    mpk_options_default(&o);
+    if (opt) {
+        if (opt->size != sizeof(mpk_options)) return fail(MPK_ERR_ARG, "mpk_options.size mismatch");
+        o = *opt;
+    }
+    if (!supported(o.val_dtype, o.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
+    mpk_plan *plan = new (std::nothrow) mpk_plan();
+    if (!plan) return fail(MPK_ERR_OOM, "host allocation failed");
+    mpk_status st = build_host_plan(A, p, cache_bytes, o, plan->hp);
+    if (st != MPK_OK) {
+        delete plan;
+        return st;
+    }
+    *out = plan;
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info) {
+    if (!plan || !info) return fail(MPK_ERR_ARG, "null argument");
+    const HostPlan &h = plan->hp;
+    std::memset(info, 0, sizeof(*info));
+    info->n = h.n;
+    info->nnz = h.nnz;
+    info->p = h.p;
+    info->nrhs = h.opt.nrhs;
+    info->n_levels = (int64_t)h.level_ptr.size() - 1;
+    info->n_groups = (int64_t)h.group_ptr.size() - 1;
+    info->n_tiles = (int64_t)h.dep_lo.size();
+    info->n_tickets = (int64_t)h.work.size();
+    info->root = h.root;
+    info->max_level_rows = h.max_level_rows;
+    info->max_group_nnz = h.max_group_nnz;
+    info->violating_groups = h.violating_groups;
+    info->device_bytes = plan->device_bytes;
+    info->workgroups = plan->workgroups;
+    info->lanes_per_row = h.lanes_per_row;
+    info->tile_nnz = h.tile_nnz;
+    info->val_dtype = h.opt.val_dtype;
+    info->plan_seconds = h.plan_seconds;
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_arrays(const mpk_plan *plan, int32_t *perm, int32_t *level_ptr, int32_t *group_ptr,
+                           int32_t *schedule) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    const HostPlan &h = plan->hp;
+    if (perm) std::copy(h.perm.begin(), h.perm.end(), perm);
+    if (level_ptr) std::copy(h.level_ptr.begin(), h.level_ptr.end(), level_ptr);
+    if (group_ptr) std::copy(h.group_ptr.begin(), h.group_ptr.end(), group_ptr);
+    if (schedule) std::copy(h.schedule.begin(), h.schedule.end(), schedule);
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_matrix(const mpk_plan *plan, int64_t *rowptr, int32_t *col, double *val) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    const HostPlan &h = plan->hp;
+    if (rowptr)
+        for (size_t i = 0; i < h.rowptr.size(); ++i) rowptr[i] = h.rowptr[i];
+    if (col) std::copy(h.col.begin(), h.col.end(), col);
+    if (val) std::copy(h.val.begin(), h.val.end(), val);
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_lo, int32_t *dep_hi,
+                          int32_t *work) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    const HostPlan &h = plan->hp;
+    if (tile_row) std::copy(h.tile_row.begin(), h.tile_row.end(), tile_row);
+    if (dep_lo) std::copy(h.dep_lo.begin(), h.dep_lo.end(), dep_lo);
+    if (dep_hi) std::copy(h.dep_hi.begin(), h.dep_hi.end(), dep_hi);
+    if (work) std::copy(h.work.begin(), h.work.end(), work);
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_upload(mpk_plan *plan) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    if (plan->uploaded) return MPK_OK;
+    HostPlan &h = plan->hp;
+    HIP_TRY(hipGetDevice(&plan->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, plan->device));
+    plan->num_cus = prop.multiProcessorCount;
+    const int64_t T = (int64_t)h.dep_lo.size();
+    const int64_t W = (int64_t)h.work.size();
+    std::vector<uint8_t> vbuf;
+    convert_values(h.val.data(), h.val.size(), h.opt.val_dtype, vbuf);
+    uint64_t bytes = 0;
+    auto &al = plan->allocs;
+    auto cleanup_fail = [&](hipError_t e, const char *what) {
+        free_all(al);
+        return fail(e == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP,
+                    std::string(what) + ": " + hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = dev_alloc(al, &plan->d_rowptr, h.n + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "rowptr");
+    if ((e = dev_alloc(al, &plan->d_col, h.nnz, &bytes)) != hipSuccess) return cleanup_fail(e, "col");
+    uint8_t *dv = nullptr;
+    if ((e = dev_alloc(al, &dv, vbuf.size(), &bytes)) != hipSuccess) return cleanup_fail(e, "val");
+    plan->d_val = dv;
+    if ((e = dev_alloc(al, &plan->d_tile_row, T + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "tiles");
+    if ((e = dev_alloc(al, &plan->d_dep_lo, T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_dep_hi, T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_work, W, &bytes)) != hipSuccess) return cleanup_fail(e, "work");
+    if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
+    if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
+    if ((e = dev_alloc(al, &plan->d_perm, h.n, &bytes)) != hipSuccess) return cleanup_fail(e, "perm");
+    struct Cp { void *d; const void *s; size_t b; } cps[] = {
+        {plan->d_rowptr, h.rowptr.data(), sizeof(int32_t) * (h.n + 1)},
+        {plan->d_col, h.col.data(), sizeof(int32_t) * h.nnz},
+        {plan->d_val, vbuf.data(), h.nnz * value_bytes(h.opt.val_dtype)},
+        {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
+        {plan->d_dep_lo, h.dep_lo.data(), sizeof(int32_t) * T},
+        {plan->d_dep_hi, h.dep_hi.data(), sizeof(int32_t) * T},
+        {plan->d_work, h.work.data(), sizeof(int32_t) * W},
+        {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
+    };
+    for (auto &c : cps)
+        if (c.b && (e = hipMemcpy(c.d, c.s, c.b, hipMemcpyHostToDevice)) != hipSuccess)
+            return cleanup_fail(e, "upload copy");
+    if ((e = hipMemset(plan->d_flags, 0, sizeof(uint32_t) * std::max<int64_t>(W, 1))) != hipSuccess)
+        return cleanup_fail(e, "flag reset");
+    if ((e = hipMemset(plan->d_ctrl, 0, sizeof(uint32_t) * kCtrlWords)) != hipSuccess)
+        return cleanup_fail(e, "ctrl reset");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup_fail(e, "upload sync");
+    // grid: all co-resident workgroups unless the caller fixes it
+    int occ = 0;
+    const void *sym = nullptr;
+    (void)dispatch_all(h.opt.val_dtype, h.opt.nrhs, false, [&](auto d) {
+        sym = decltype(d)::mpk_symbol(h.lanes_per_row);
+        return hipSuccess;
+    });
+    if (sym && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sym, kBlock, 0) != hipSuccess) occ = 0;
+    if (occ <= 0) occ = 2;
+    int64_t wg = h.opt.workgroups > 0 ? h.opt.workgroups : (int64_t)occ * plan->num_cus;
+    wg = std::max<int64_t>(1, std::min<int64_t>(wg, std::max<int64_t>(W, 1)));
+    plan->workgroups = (int32_t)wg;
+    plan->device_bytes = bytes;
+    plan->uploaded = true;
+    return MPK_OK;
+}
+
+mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int32_t k, int32_t to_plan,
+                       void *stream) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    if (!plan->uploaded) return fail(MPK_ERR_STATE, "plan not uploaded");
+    if (k < 1 || k > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "k out of range");
+    if (plan->hp.n == 0) return MPK_OK;
+    if (!in || !out) return fail(MPK_ERR_ARG, "null vector");
+    if (in == out) return fail(MPK_ERR_ARG, "in and out alias");
+    const int64_t total = plan->hp.n * k;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (to_plan)
+        hipLaunchKernelGGL(permute_gather, dim3(blocks), dim3(256), 0, s, in, out, plan->d_perm, plan->hp.n, k);
+    else
+        hipLaunchKernelGGL(permute_scatter, dim3(blocks), dim3(256), 0, s, in, out, plan->d_perm, plan->hp.n, k);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+static mpk_status check_run_args(mpk_plan *plan, const double *X, double *Y) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    if (!plan->uploaded) return fail(MPK_ERR_STATE, "plan not uploaded (call mpk_plan_upload)");
+    if (plan->hp.n > 0 && (!X || !Y)) return fail(MPK_ERR_ARG, "null vector");
+    const int64_t NK = plan->hp.n * plan->hp.opt.nrhs;
+    const double *y0 = Y, *y1 = Y + NK * plan->hp.p;
+    if (plan->hp.n > 0 && X + NK > y0 && X < y1) return fail(MPK_ERR_ARG, "Y overlaps X");
+    return MPK_OK;
+}
+
+mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec, void *stream) {
+    mpk_status st = check_run_args(plan, X, Y);
+    if (st != MPK_OK) return st;
+    HostPlan &h = plan->hp;
+    if (h.n == 0) return MPK_OK;
+    RecArgs ra;
+    if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
+    if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
+        return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
+    plan->epoch += 1;
+    if (plan->epoch == 0) plan->epoch = 1;
+    MpkArgs a;
+    a.rowptr = plan->d_rowptr;
+    a.col = plan->d_col;
+    a.val = plan->d_val;
+    a.tile_row = plan->d_tile_row;
+    a.dep_lo = plan->d_dep_lo;
+    a.dep_hi = plan->d_dep_hi;
+    a.work = plan->d_work;
+    a.n = (int32_t)h.n;
+    a.ntiles = (int32_t)h.dep_lo.size();
+    a.ntickets = (int32_t)h.work.size();
+    a.X = X;
+    a.Y = Y;
+    a.flags = plan->d_flags;
+    a.ctrl = plan->d_ctrl;
+    a.epoch = plan->epoch;
+    a.watchdog = h.opt.watchdog_spins > 0 ? h.opt.watchdog_spins : (int64_t)1 << 24;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.nrhs, rec != nullptr, [&](auto d) {
+        return decltype(d)::mpk(h.lanes_per_row, plan->workgroups, s, a, ra);
+    });
+    if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("mpk launch: ") + hipGetErrorString(e));
+    return MPK_OK;
+}
+
+mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec,
+                            void *stream) {
+    mpk_status st = check_run_args(plan, X, Y);
+    if (st != MPK_OK) return st;
+    HostPlan &h = plan->hp;
+    if (h.n == 0) return MPK_OK;
+    RecArgs ra;
+    if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
+    if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
+        return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
+    const int K = h.opt.nrhs, G = h.lanes_per_row;
+    const int rpb = rows_per_block_for(G);
+    const int blocks = (int)((h.n + rpb - 1) / rpb);
+    const int64_t NK = h.n * K;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int q = 1; q <= h.p; ++q) {
+        const double *x = q == 1 ? X : Y + (int64_t)(q - 2) * NK;
+        double *y = Y + (int64_t)(q - 1) * NK;
+        const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
+        hipError_t e = dispatch_all(h.opt.val_dtype, K, rec != nullptr, [&](auto d) {
+            return decltype(d)::spmv(G, blocks, rpb, s, plan->d_rowptr, plan->d_col, plan->d_val, (int)h.n, x,
+                                     y, q, yq2, ra);
+        });
+        if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
+    }
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_status(mpk_plan *plan, void *stream) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    if (!plan->uploaded) return fail(MPK_ERR_STATE, "plan not uploaded");
+    HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+    uint32_t ctrl[4];
+    HIP_TRY(hipMemcpy(ctrl, plan->d_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost));
+    if (plan->epoch != 0 && ctrl[2] == plan->epoch)
+        return fail(MPK_ERR_TIMEOUT, "dependency wait timed out at ticket " + std::to_string(ctrl[3]));
+    return MPK_OK;
+}
+
+void mpk_plan_destroy(mpk_plan *plan) {
+    if (!plan) return;
+    free_all(plan->allocs);
+    delete plan;
+}
+
+mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out) {
+    if (!out) return fail(MPK_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    mpk_options o;
+    mpk_options_default(&o);
+    if (opt) {
+        if (opt->size != sizeof(mpk_options)) return fail(MPK_ERR_ARG, "mpk_options.size mismatch");
+        o = *opt;
+    }
+    mpk_status st = validate_csr(A);
+    if (st != MPK_OK) return st;
+    if (o.nrhs < 1 || o.nrhs > MPK_MAX_NRHS || !supported(o.val_dtype, o.nrhs, false))
+        return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
+    if (o.lanes_per_row != 0) {
+        int g = o.lanes_per_row;
+        if (g < 4 || g > 64 || (g & (g - 1)) || g < o.nrhs)
+            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
+    }
+    mpk_spmv *h = new (std::nothrow) mpk_spmv();
+    if (!h) return fail(MPK_ERR_OOM, "host allocation failed");
+    h->n = A->n;
+    h->nnz = A->nnz;
+    h->dtype = o.val_dtype;
+    h->nrhs = o.nrhs;
+    double mean_row = A->n > 0 ? (double)A->nnz / (double)A->n : 1.0;
+    h->lanes = o.lanes_per_row ? o.lanes_per_row : auto_lanes(mean_row, o.nrhs);
+    std::vector<int32_t> rp(A->n + 1);
+    for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
+    std::vector<uint8_t> vbuf;
+    convert_values(A->val, A->nnz, o.val_dtype, vbuf);
+    hipError_t e;
+    uint8_t *dv = nullptr;
+    if ((e = dev_alloc(h->allocs, &h->d_rowptr, A->n + 1)) != hipSuccess ||
+        (e = dev_alloc(h->allocs, &h->d_col, A->nnz)) != hipSuccess ||
+        (e = dev_alloc(h->allocs, &dv, vbuf.size())) != hipSuccess) {
+        free_all(h->allocs);
+        delete h;
+        return fail(e == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP, hipGetErrorString(e));
+    }
+    h->d_val = dv;
+    if ((e = hipMemcpy(h->d_rowptr, rp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (A->nnz && (e = hipMemcpy(h->d_col, A->col, sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice)) !=
+                       hipSuccess) ||
+        (A->nnz && (e = hipMemcpy(h->d_val, vbuf.data(), A->nnz * value_bytes(o.val_dtype),
+                                  hipMemcpyHostToDevice)) != hipSuccess)) {
+        free_all(h->allocs);
+        delete h;
+        return fail(MPK_ERR_HIP, hipGetErrorString(e));
+    }
+    *out = h;
+    return MPK_OK;
+}
+
+static mpk_status spmv_launch(mpk_spmv *h, const double *x, double *y, hipStream_t s) {
+    const int G = h->lanes, rpb = rows_per_block_for(G);
+    const int blocks = (int)((h->n + rpb - 1) / rpb);
+    RecArgs ra;
+    fill_rec(nullptr, 1, h->nrhs, ra);
+    hipError_t e = dispatch_all(h->dtype, h->nrhs, false, [&](auto d) {
+        return decltype(d)::spmv(G, blocks, rpb, s, h->d_rowptr, h->d_col, h->d_val, (int)h->n, x, y, 1,
+                                 nullptr, ra);
+    });
+    if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
+    return MPK_OK;
+}
+
+mpk_status spmv_run(mpk_spmv *h, const double *x, double *y, void *stream) {
+    if (!h) return fail(MPK_ERR_ARG, "null handle");
+    if (h->n == 0) return MPK_OK;
+    if (!x || !y) return fail(MPK_ERR_ARG, "null vector");
+    if (x == y) return fail(MPK_ERR_ARG, "x and y alias");
+    return spmv_launch(h, x, y, reinterpret_cast<hipStream_t>(stream));
+}
+
+mpk_status spmv_powers_run(mpk_spmv *h, int32_t p, const double *X, double *Y, void *stream) {
+    if (!h) return fail(MPK_ERR_ARG, "null handle");
+    if (p < 1 || p > 4096) return fail(MPK_ERR_ARG, "p out of range");
+    if (h->n == 0) return MPK_OK;
+    if (!X || !Y) return fail(MPK_ERR_ARG, "null vector");
+    const int64_t NK = h->n * h->nrhs;
+    for (int q = 1; q <= p; ++q) {
+        const double *x = q == 1 ? X : Y + (q - 2) * NK;
+        mpk_status st = spmv_launch(h, x, Y + (q - 1) * NK, reinterpret_cast<hipStream_t>(stream));
+        if (st != MPK_OK) return st;
+    }
+    return MPK_OK;
+}
+
+void spmv_destroy(mpk_spmv *h) {
+    if (!h) return;
+    free_all(h->allocs);
+    delete h;
+}
+
+mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups, double *sink,
+                        void *stream) {
+    if (!buf || !sink) return fail(MPK_ERR_ARG, "null pointer");
+    if (bytes % 16 || ((uintptr_t)buf % 16)) return fail(MPK_ERR_ARG, "buffer must be 16-byte aligned");
+    if (reps < 1 || workgroups < 1) return fail(MPK_ERR_ARG, "reps and workgroups must be >= 1");
+    hipLaunchKernelGGL(bw_probe, dim3(workgroups), dim3(kBlock), 0, reinterpret_cast<hipStream_t>(stream),
+                       reinterpret_cast<const double2 *>(buf), (int64_t)(bytes / 16), reps, sink);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+}  // extern "C"

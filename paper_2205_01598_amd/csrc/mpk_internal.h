@@ -1,0 +1,63 @@
+// Internal definitions shared by the host planner (plan.cpp) and the HIP
+// side of the library (mpk_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mpk.h"
+
+namespace mpk {
+
+// Thread-local error message behind mpk_last_error().
+void set_error(const std::string &msg);
+mpk_status fail(mpk_status s, const std::string &msg);
+
+// Host-side state of a plan, filled by the planner.
+struct HostPlan {
+    int64_t n = 0, nnz = 0;
+    int32_t p = 1;
+    uint64_t cache_bytes = 0;
+    mpk_options opt{};
+    int64_t root = 0;
+
+    std::vector<int32_t> perm;       // new -> old
+    std::vector<int32_t> iperm;      // old -> new
+    std::vector<int32_t> level_ptr;  // L+1
+    std::vector<int64_t> level_nnz;  // L
+    std::vector<int32_t> group_ptr;  // G+1, indices into levels
+    std::vector<int32_t> schedule;   // 3*G*p: (d, p, i)
+
+    // renumbered matrix P A P^T, columns ascending per row
+    std::vector<int32_t> rowptr;     // n+1 (nnz < 2^31)
+    std::vector<int32_t> col;
+    std::vector<double> val;
+
+    // device tiles: row ranges inside level groups
+    std::vector<int32_t> tile_row;   // n_tiles+1
+    std::vector<int32_t> tile_group; // n_tiles
+    std::vector<int32_t> dep_lo, dep_hi;  // n_tiles
+    std::vector<int32_t> group_tile; // G+1
+    std::vector<int32_t> work;       // tickets: tile*64 + (q-1)
+
+    int64_t max_level_rows = 0, max_group_nnz = 0, violating_groups = 0;
+    int32_t lanes_per_row = 0;
+    int32_t tile_nnz = 0;
+    double plan_seconds = 0.0;
+};
+
+// Runs every host step of the plan.  Returns MPK_OK or an error (message set).
+mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
+                           const mpk_options &opt, HostPlan &hp);
+
+// Validation shared by plan and SpMV creation.
+mpk_status validate_csr(const mpk_csr *A);
+
+// Default lanes-per-row choice for a mean row length and k columns.
+int32_t auto_lanes(double mean_row, int32_t k);
+
+// Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
+int32_t bytes_per_nnz(int32_t dtype);
+
+}  // namespace mpk

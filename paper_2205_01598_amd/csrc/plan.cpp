@@ -1,0 +1,425 @@
+// Host planner of the level-blocked MPK: CSR validation, the graph of
+// A + A^T, BFS levels (Eq. 3) with level-by-level renumbering (Sec. 4.1),
+// level groups under Eq. (5) (Sec. 4.3), the diagonal order of the Lp
+// diagram (Sec. 4.2, Fig. 6), the renumbered matrix and the device tile
+// table with point-to-point dependency ranges (Sec. 4.3).
+//
+// Everything here runs on the CPU; nothing touches the GPU.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "mpk_internal.h"
+
+namespace mpk {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string &msg) { g_err = msg; }
+mpk_status fail(mpk_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+const char *last_error_cstr() { return g_err.c_str(); }
+
+int32_t bytes_per_nnz(int32_t dtype) {
+    switch (dtype) {
+        case MPK_F32: return 8;
+        case MPK_BF16: return 6;
+        default: return 12;
+    }
+}
+
+int32_t auto_lanes(double mean_row, int32_t k) {
+    // enough lanes that one pass covers most of a row, at least k
+    int32_t g = 4;
+    double per_slot = mean_row;
+    while (g < 64 && (double)(g / std::max<int32_t>(1, k)) < per_slot * 0.75) g <<= 1;
+    while (g < k) g <<= 1;
+    return std::min<int32_t>(std::max<int32_t>(g, 4), 64);
+}
+
+mpk_status validate_csr(const mpk_csr *A) {
+    if (!A) return fail(MPK_ERR_ARG, "null matrix");
+    if (A->n < 0) return fail(MPK_ERR_CSR, "negative n");
+    if (A->n > (int64_t)std::numeric_limits<int32_t>::max() - 1)
+        return fail(MPK_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+    if (A->nnz < 0) return fail(MPK_ERR_CSR, "negative nnz");
+    if (A->nnz > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(MPK_ERR_UNSUPPORTED, "nnz >= 2^31 is not supported");
+    if (!A->rowptr) return fail(MPK_ERR_ARG, "null rowptr");
+    if (A->nnz > 0 && (!A->col || !A->val)) return fail(MPK_ERR_ARG, "null col/val");
+    if (A->rowptr[0] != 0) return fail(MPK_ERR_CSR, "rowptr[0] != 0");
+    for (int64_t i = 0; i < A->n; ++i)
+        if (A->rowptr[i + 1] < A->rowptr[i]) return fail(MPK_ERR_CSR, "rowptr not monotone");
+    if (A->rowptr[A->n] != A->nnz) return fail(MPK_ERR_CSR, "rowptr[n] != nnz");
+    const int64_t n = A->n;
+    for (int64_t j = 0; j < A->nnz; ++j)
+        if (A->col[j] < 0 || A->col[j] >= n) return fail(MPK_ERR_CSR, "column index out of range");
+    return MPK_OK;
+}
+
+namespace {
+
+// Undirected graph of A: u ~ v (u != v) iff A_uv or A_vu is stored.
+// Neighbour lists are sorted ascending and free of duplicates.
+struct Graph {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> adj;
+    int64_t deg(int64_t u) const { return ptr[u + 1] - ptr[u]; }
+};
+
+void build_graph(const mpk_csr *A, Graph &g) {
+    const int64_t n = A->n;
+    // transpose by counting sort; walking rows in order leaves every
+    // transposed row sorted
+    std::vector<int64_t> tptr(n + 1, 0);
+    for (int64_t j = 0; j < A->nnz; ++j) tptr[A->col[j] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    std::vector<int32_t> tadj(std::max<int64_t>(A->nnz, 1));
+    {
+        std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t j = A->rowptr[r]; j < A->rowptr[r + 1]; ++j) tadj[pos[A->col[j]]++] = (int32_t)r;
+    }
+    // rows of A, sorted copies where needed
+    std::vector<int32_t> rowbuf;
+    g.ptr.assign(n + 1, 0);
+    // upper bound of each merged list, then compact after merging
+    std::vector<int64_t> ub(n + 1, 0);
+    for (int64_t u = 0; u < n; ++u)
+        ub[u + 1] = ub[u] + (A->rowptr[u + 1] - A->rowptr[u]) + (tptr[u + 1] - tptr[u]);
+    std::vector<int32_t> tmp(std::max<int64_t>(ub[n], 1));
+    std::vector<int64_t> len(n, 0);
+#pragma omp parallel
+    {
+        std::vector<int32_t> rb;
+#pragma omp for schedule(dynamic, 4096)
+        for (int64_t u = 0; u < n; ++u) {
+            const int32_t *ra = A->col + A->rowptr[u];
+            int64_t na = A->rowptr[u + 1] - A->rowptr[u];
+            if (!std::is_sorted(ra, ra + na)) {
+                rb.assign(ra, ra + na);
+                std::sort(rb.begin(), rb.end());
+                ra = rb.data();
+            }
+            const int32_t *rt = tadj.data() + tptr[u];
+            int64_t nt = tptr[u + 1] - tptr[u];
+            int32_t *o = tmp.data() + ub[u];
+            int64_t a = 0, b = 0, m = 0;
+            int64_t last = -1;
+            while (a < na || b < nt) {
+                int32_t v;
+                if (b >= nt || (a < na && ra[a] <= rt[b])) v = ra[a++];
+                else v = rt[b++];
+                if (v == u || v == last) continue;
+                o[m++] = v;
+                last = v;
+            }
+            len[u] = m;
+        }
+    }
+    for (int64_t u = 0; u < n; ++u) g.ptr[u + 1] = g.ptr[u] + len[u];
+    g.adj.resize(std::max<int64_t>(g.ptr[n], 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t u = 0; u < n; ++u)
+        std::memcpy(g.adj.data() + g.ptr[u], tmp.data() + ub[u], sizeof(int32_t) * len[u]);
+}
+
+// Distances from root inside its component; returns the eccentricity.
+int64_t bfs_distance(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &dist,
+                     std::vector<int32_t> &queue) {
+    std::fill(dist.begin(), dist.end(), -1);
+    int64_t head = 0, tail = 0;
+    dist[root] = 0;
+    queue[tail++] = (int32_t)root;
+    int32_t far = 0;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        int32_t du = dist[u];
+        for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+            int32_t v = g.adj[j];
+            if (dist[v] < 0) {
+                dist[v] = du + 1;
+                far = du + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    return far;
+}
+
+// George-Liu pseudo-peripheral search from `start`: move to the
+// smallest-degree vertex (lowest index on ties) of the farthest level while
+// that raises the eccentricity.
+int64_t peripheral_root(const Graph &g, int64_t n, int64_t start) {
+    std::vector<int32_t> dist(n), queue(n);
+    int64_t r = start;
+    int64_t ecc = bfs_distance(g, n, r, dist, queue);
+    for (;;) {
+        int64_t best = -1, bestdeg = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            if (dist[v] != ecc) continue;
+            int64_t d = g.deg(v);
+            if (best < 0 || d < bestdeg) {
+                best = v;
+                bestdeg = d;
+            }
+        }
+        int64_t e2 = bfs_distance(g, n, best, dist, queue);
+        if (e2 > ecc) {
+            r = best;
+            ecc = e2;
+        } else {
+            return r;
+        }
+    }
+}
+
+// Queue BFS (Eq. 3).  The queue order is the new numbering: each vertex of
+// level i, taken in new order, appends its not yet numbered neighbours in
+// ascending original index, so level i+1 comes out contiguous and in
+// discovery order.  An empty frontier with vertices left starts the next
+// level at the smallest unnumbered original index.
+void bfs_levels(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &perm,
+                std::vector<int32_t> &level_ptr) {
+    perm.assign(n, 0);
+    level_ptr.clear();
+    level_ptr.push_back(0);
+    if (n == 0) return;
+    std::vector<uint8_t> seen(n, 0);
+    int64_t tail = 0, head = 0, scan = 0;
+    perm[tail++] = (int32_t)root;
+    seen[root] = 1;
+    int64_t level_end = tail;
+    while (head < n) {
+        if (head == tail) {  // frontier exhausted: next component, own level
+            while (seen[scan]) ++scan;
+            perm[tail++] = (int32_t)scan;
+            seen[scan] = 1;
+            level_end = tail;
+        }
+        int32_t u = perm[head++];
+        for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+            int32_t v = g.adj[j];
+            if (!seen[v]) {
+                seen[v] = 1;
+                perm[tail++] = v;
+            }
+        }
+        if (head == level_end) {
+            level_ptr.push_back((int32_t)head);
+            level_end = tail;
+        }
+    }
+}
+
+}  // namespace
+
+mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
+                           const mpk_options &opt, HostPlan &hp) {
+    auto t0 = std::chrono::steady_clock::now();
+    mpk_status st = validate_csr(A);
+    if (st != MPK_OK) return st;
+    if (p < 1 || p > MPK_MAX_POWER) return fail(MPK_ERR_ARG, "p must be in [1, 32]");
+    if (cache_bytes == 0) return fail(MPK_ERR_ARG, "cache budget must be > 0");
+    if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
+    if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
+    if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
+    if (opt.root_mode < 0 || opt.root_mode > 1) return fail(MPK_ERR_ARG, "bad root_mode");
+    if (opt.lanes_per_row != 0) {
+        int32_t g = opt.lanes_per_row;
+        if (g < 4 || g > 64 || (g & (g - 1)) || g < opt.nrhs)
+            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
+    }
+    if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
+
+    const int64_t n = A->n;
+    hp.n = n;
+    hp.nnz = A->nnz;
+    hp.p = p;
+    hp.cache_bytes = cache_bytes;
+    hp.opt = opt;
+
+    try {
+        // ---- graph, root, levels -------------------------------------------------
+        Graph g;
+        build_graph(A, g);
+        hp.root = 0;
+        if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
+        bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+        { Graph().adj.swap(g.adj); }
+        hp.iperm.assign(n, 0);
+        for (int64_t i = 0; i < n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
+        const int64_t L = (int64_t)hp.level_ptr.size() - 1;
+
+        // ---- nonzeros per level ------------------------------------------------------
+        hp.level_nnz.assign(L, 0);
+        hp.max_level_rows = 0;
+        for (int64_t l = 0; l < L; ++l) {
+            int64_t s = 0;
+            for (int64_t r = hp.level_ptr[l]; r < hp.level_ptr[l + 1]; ++r) {
+                int64_t o = hp.perm[r];
+                s += A->rowptr[o + 1] - A->rowptr[o];
+            }
+            hp.level_nnz[l] = s;
+            hp.max_level_rows = std::max<int64_t>(hp.max_level_rows, hp.level_ptr[l + 1] - hp.level_ptr[l]);
+        }
+
+        // ---- level groups, Eq. (5) ----------------------------------------------------
+        const int64_t bnz = bytes_per_nnz(opt.val_dtype);
+        const uint64_t budget = (uint64_t)std::floor(opt.safety_factor * (double)cache_bytes);
+        auto group_bytes = [&](int64_t nz, int64_t rows) -> unsigned __int128 {
+            unsigned __int128 per = (unsigned __int128)nz * (uint64_t)bnz;
+            if (opt.budget_vectors) per += (unsigned __int128)rows * 8u * (uint64_t)opt.nrhs;
+            return per * (uint64_t)(p + 1);
+        };
+        hp.group_ptr.clear();
+        hp.group_ptr.push_back(0);
+        hp.max_group_nnz = 0;
+        hp.violating_groups = 0;
+        for (int64_t l = 0; l < L;) {
+            int64_t nz = hp.level_nnz[l];
+            int64_t rows = hp.level_ptr[l + 1] - hp.level_ptr[l];
+            int64_t e = l + 1;
+            while (e < L) {
+                int64_t nz2 = nz + hp.level_nnz[e];
+                int64_t rows2 = rows + (hp.level_ptr[e + 1] - hp.level_ptr[e]);
+                if (!(group_bytes(nz2, rows2) < (unsigned __int128)budget)) break;
+                nz = nz2;
+                rows = rows2;
+                ++e;
+            }
+            if (!(group_bytes(nz, rows) < (unsigned __int128)budget)) hp.violating_groups++;
+            hp.max_group_nnz = std::max(hp.max_group_nnz, nz);
+            hp.group_ptr.push_back((int32_t)e);
+            l = e;
+        }
+        const int64_t G = (int64_t)hp.group_ptr.size() - 1;
+
+        // ---- Lp diagonal order, Fig. 6 ----------------------------------------------
+        hp.schedule.clear();
+        hp.schedule.reserve(3 * G * p);
+        for (int64_t d = 1; d <= G + p - 1; ++d) {
+            int64_t q0 = std::max<int64_t>(1, d - (G - 1)), q1 = std::min<int64_t>(d, p);
+            for (int64_t q = q0; q <= q1; ++q) {
+                hp.schedule.push_back((int32_t)d);
+                hp.schedule.push_back((int32_t)q);
+                hp.schedule.push_back((int32_t)(d - q));
+            }
+        }
+
+        // ---- renumbered matrix P A P^T -------------------------------------------------
+        hp.rowptr.assign(n + 1, 0);
+        for (int64_t r = 0; r < n; ++r) {
+            int64_t o = hp.perm[r];
+            hp.rowptr[r + 1] = hp.rowptr[r] + (int32_t)(A->rowptr[o + 1] - A->rowptr[o]);
+        }
+        hp.col.resize(A->nnz);
+        hp.val.resize(A->nnz);
+#pragma omp parallel
+        {
+            std::vector<std::pair<int32_t, double>> buf;
+#pragma omp for schedule(dynamic, 2048)
+            for (int64_t r = 0; r < n; ++r) {
+                int64_t o = hp.perm[r];
+                int64_t a = A->rowptr[o], b = A->rowptr[o + 1];
+                buf.resize(b - a);
+                for (int64_t j = a; j < b; ++j) buf[j - a] = {hp.iperm[A->col[j]], A->val[j]};
+                std::stable_sort(buf.begin(), buf.end(),
+                                 [](const auto &x, const auto &y) { return x.first < y.first; });
+                int64_t out = hp.rowptr[r];
+                for (size_t t = 0; t < buf.size(); ++t) {
+                    hp.col[out + t] = buf[t].first;
+                    hp.val[out + t] = buf[t].second;
+                }
+            }
+        }
+
+        // ---- device tiles --------------------------------------------------------------
+        int64_t tile_nnz = opt.tile_nnz;
+        if (tile_nnz <= 0) tile_nnz = 32768;
+        const int64_t max_tile_rows = 1 << 14;
+        hp.tile_nnz = (int32_t)tile_nnz;
+        double mean_row = n > 0 ? (double)A->nnz / (double)n : 1.0;
+        hp.lanes_per_row = opt.lanes_per_row ? opt.lanes_per_row : auto_lanes(mean_row, opt.nrhs);
+        hp.tile_row.clear();
+        hp.tile_group.clear();
+        hp.group_tile.clear();
+        for (int64_t gi = 0; gi < G; ++gi) {
+            hp.group_tile.push_back((int32_t)hp.tile_group.size());
+            int64_t r0 = hp.level_ptr[hp.group_ptr[gi]];
+            int64_t r1 = hp.level_ptr[hp.group_ptr[gi + 1]];
+            int64_t gnz = hp.rowptr[r1] - hp.rowptr[r0];
+            // equal-nonzero split of the group into ceil(gnz / tile_nnz) tiles
+            int64_t nt = std::max<int64_t>(1, (gnz + tile_nnz - 1) / tile_nnz);
+            nt = std::min<int64_t>(nt, r1 - r0);
+            std::vector<int64_t> bnd;
+            bnd.push_back(r0);
+            for (int64_t t = 1; t < nt; ++t) {
+                int64_t target = hp.rowptr[r0] + (gnz * t) / nt;
+                int64_t lo = bnd.back() + 1, hi = r1 - (nt - t);
+                int64_t a = std::lower_bound(hp.rowptr.begin() + lo, hp.rowptr.begin() + hi + 1,
+                                             (int32_t)target) - hp.rowptr.begin();
+                bnd.push_back(std::min<int64_t>(std::max<int64_t>(a, lo), hi));
+            }
+            bnd.push_back(r1);
+            for (size_t t = 0; t + 1 < bnd.size(); ++t) {
+                for (int64_t r = bnd[t]; r < bnd[t + 1]; r += max_tile_rows) {
+                    hp.tile_row.push_back((int32_t)r);
+                    hp.tile_group.push_back((int32_t)gi);
+                }
+            }
+        }
+        hp.group_tile.push_back((int32_t)hp.tile_group.size());
+        hp.tile_row.push_back((int32_t)n);
+        const int64_t T = (int64_t)hp.tile_group.size();
+
+        // dependency range of each tile: every tile holding a column its rows
+        // read, plus the tile itself (its own rows at power q-1)
+        hp.dep_lo.assign(T, 0);
+        hp.dep_hi.assign(T, 0);
+        bool bad = false;
+#pragma omp parallel for schedule(dynamic, 16) reduction(|| : bad)
+        for (int64_t t = 0; t < T; ++t) {
+            int64_t r0 = hp.tile_row[t], r1 = hp.tile_row[t + 1];
+            int64_t lo = r0, hi = r1 - 1;
+            for (int64_t j = hp.rowptr[r0]; j < hp.rowptr[r1]; ++j) {
+                lo = std::min<int64_t>(lo, hp.col[j]);
+                hi = std::max<int64_t>(hi, hp.col[j]);
+            }
+            int64_t tl = std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)lo) -
+                         hp.tile_row.begin() - 1;
+            int64_t th = std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)hi) -
+                         hp.tile_row.begin() - 1;
+            hp.dep_lo[t] = (int32_t)tl;
+            hp.dep_hi[t] = (int32_t)th;
+            // Eq. (4): a level only touches its neighbour levels, so a tile
+            // only depends on tiles of its own and the two adjacent groups
+            int64_t gi = hp.tile_group[t];
+            if (hp.tile_group[tl] < gi - 1 || hp.tile_group[th] > gi + 1) bad = true;
+        }
+        if (bad) return fail(MPK_ERR_CSR, "internal: tile dependency crosses more than one level group");
+
+        // tickets in Lp diagonal order, tiles of a node in row order
+        hp.work.clear();
+        hp.work.reserve(T * p);
+        for (size_t s = 0; s < hp.schedule.size(); s += 3) {
+            int32_t q = hp.schedule[s + 1], gi = hp.schedule[s + 2];
+            for (int32_t t = hp.group_tile[gi]; t < hp.group_tile[gi + 1]; ++t)
+                hp.work.push_back(t * 64 + (q - 1));
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(MPK_ERR_OOM, "host allocation failed while planning");
+    }
+    hp.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MPK_OK;
+}
+
+}  // namespace mpk

@@ -1,0 +1,181 @@
+"""Python face of the MPK library: thin wrappers over the C-ABI.
+
+PyTorch only supplies device memory (tensors) and streams; every step of the
+computation runs in the library's HIP kernels or its C++ planner.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, default_options, lib
+
+
+def _csr_struct(n, rowptr, col, val):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    s = _lib.mpk_csr(int(n), int(rowptr[-1]) if len(rowptr) else 0,
+                     rowptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                     col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                     val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return s, (rowptr, col, val)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _f64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Recurrence:
+    """Three-term recurrence epilogue (see ``mpk_recurrence`` in include/mpk.h)."""
+
+    def __init__(self, alpha, beta=None, gamma=None, coef=None, complex_pairs=False,
+                 y_prev=None, acc=None):
+        p = len(alpha)
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        self.beta = np.ascontiguousarray(beta if beta is not None else np.zeros(p), dtype=np.float64)
+        self.gamma = np.ascontiguousarray(gamma if gamma is not None else np.zeros(p), dtype=np.float64)
+        self.coef = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+        self.complex_pairs = bool(complex_pairs)
+        self.y_prev = y_prev
+        self.acc = acc
+
+    def struct(self):
+        return _lib.mpk_recurrence(
+            _f64p(self.alpha), _f64p(self.beta), _f64p(self.gamma),
+            _f64p(self.coef) if self.coef is not None else None,
+            int(self.complex_pairs),
+            int(self.y_prev.data_ptr()) if self.y_prev is not None else None,
+            int(self.acc.data_ptr()) if self.acc is not None else None)
+
+
+class Plan:
+    """``mpk_plan``: preprocessing (levels, level groups, Lp schedule, tiles)
+    plus the device copy of the renumbered matrix."""
+
+    def __init__(self, A, p: int, cache_bytes: int, *, upload: bool = True, **opts):
+        self._h = None
+        s, keep = _csr_struct(A.n, A.rowptr, A.col, A.val)
+        o = default_options(**opts)
+        h = ctypes.c_void_p()
+        check(lib().mpk_plan_create(ctypes.byref(s), int(p), int(cache_bytes), ctypes.byref(o),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.n = int(A.n)
+        self.nnz = int(s.nnz)
+        self.p = int(p)
+        self.nrhs = int(o.nrhs)
+        if upload:
+            self.upload()
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib._lib is not None:
+            lib().mpk_plan_destroy(self._h)
+            self._h = None
+
+    def upload(self):
+        check(lib().mpk_plan_upload(self._h))
+
+    def info(self) -> dict:
+        i = _lib.mpk_plan_info()
+        check(lib().mpk_plan_query(self._h, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in i._fields_}
+
+    def arrays(self):
+        inf = self.info()
+        n, L, G = inf["n"], inf["n_levels"], inf["n_groups"]
+        perm = np.empty(n, np.int32)
+        lp = np.empty(L + 1, np.int32)
+        gp = np.empty(G + 1, np.int32)
+        sch = np.empty(3 * G * self.p, np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        check(lib().mpk_plan_arrays(self._h, perm.ctypes.data_as(P), lp.ctypes.data_as(P),
+                                    gp.ctypes.data_as(P), sch.ctypes.data_as(P)))
+        return perm, lp, gp, sch.reshape(-1, 3)
+
+    def matrix(self):
+        rowptr = np.empty(self.n + 1, np.int64)
+        col = np.empty(self.nnz, np.int32)
+        val = np.empty(self.nnz, np.float64)
+        check(lib().mpk_plan_matrix(self._h, rowptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _f64p(val)))
+        return rowptr, col, val
+
+    def tiles(self):
+        inf = self.info()
+        T, W = inf["n_tiles"], inf["n_tickets"]
+        tr = np.empty(T + 1, np.int32)
+        lo = np.empty(T, np.int32)
+        hi = np.empty(T, np.int32)
+        work = np.empty(W, np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        check(lib().mpk_plan_tiles(self._h, tr.ctypes.data_as(P), lo.ctypes.data_as(P),
+                                   hi.ctypes.data_as(P), work.ctypes.data_as(P)))
+        return tr, lo, hi, work
+
+    # -- device calls ------------------------------------------------------------
+    def permute(self, x, out, to_plan: bool, stream=None):
+        k = 1 if x.dim() == 1 else x.shape[-1]
+        check(lib().mpk_permute(self._h, _ptr(x), _ptr(out), int(k), int(to_plan), _stream(stream)))
+        return out
+
+    def run(self, X, Y, rec: Recurrence | None = None, stream=None):
+        r = ctypes.byref(rec.struct()) if rec is not None else None
+        check(lib().mpk_run(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+        return Y
+
+    def run_baseline(self, X, Y, rec: Recurrence | None = None, stream=None):
+        r = ctypes.byref(rec.struct()) if rec is not None else None
+        check(lib().mpk_run_baseline(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+        return Y
+
+    def status(self, stream=None):
+        check(lib().mpk_plan_status(self._h, _stream(stream)))
+
+
+class Spmv:
+    """``mpk_spmv``: baseline SpMV on a matrix in its given order."""
+
+    def __init__(self, A, **opts):
+        self._h = None
+        s, keep = _csr_struct(A.n, A.rowptr, A.col, A.val)
+        o = default_options(**opts)
+        h = ctypes.c_void_p()
+        check(lib().spmv_create(ctypes.byref(s), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n = int(A.n)
+        self.nrhs = int(o.nrhs)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib._lib is not None:
+            lib().spmv_destroy(self._h)
+            self._h = None
+
+    def run(self, x, y, stream=None):
+        check(lib().spmv_run(self._h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def powers(self, p: int, X, Y, stream=None):
+        check(lib().spmv_powers_run(self._h, int(p), _ptr(X), _ptr(Y), _stream(stream)))
+        return Y
+
+
+def bw_probe(buf, reps: int, workgroups: int, sink, stream=None):
+    nbytes = buf.numel() * buf.element_size()
+    check(lib().mpk_bw_probe(_ptr(buf), int(nbytes), int(reps), int(workgroups), _ptr(sink),
+                             _stream(stream)))

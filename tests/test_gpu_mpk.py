@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+FP64 bar: ||y_p - y_p^oracle||_2 / ||y_p^oracle||_2 <= 1e-12 for every power
+(the summation order differs from the oracle's, so not bit for bit), and bit
+equality where the inputs make every partial sum an exact integer.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2205_01598_amd import MpkError, Plan, Recurrence, Spmv  # noqa: E402
+
+TOL = 1e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _to_plan(x, perm):
+    return x[perm.astype(np.int64)]
+
+
+def _from_plan(y, perm):
+    out = np.empty_like(y)
+    out[..., perm.astype(np.int64), :] = y if y.ndim == 3 else y[..., None]
+    return out
+
+
+def _unpermute_powers(Y, perm):
+    # Y: (p, n[, k]) in plan order -> original order
+    out = np.empty_like(Y)
+    out[:, perm.astype(np.int64)] = Y
+    return out
+
+
+def _rel_err(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def run_mpk(A, x, p, C, baseline=False, **opts):
+    dev = _dev()
+    pl = Plan(A, p, C, **opts)
+    perm = pl.arrays()[0]
+    xp = _to_plan(x, perm)
+    X = torch.from_numpy(np.ascontiguousarray(xp)).to(dev)
+    Y = torch.full((p,) + tuple(X.shape), float("nan"), dtype=torch.float64, device=dev)
+    (pl.run_baseline if baseline else pl.run)(X, Y)
+    pl.status()
+    torch.cuda.synchronize()
+    return _unpermute_powers(Y.cpu().numpy(), perm), pl
+
+
+def check_powers(Y, ref, tol=TOL):
+    for q in range(ref.shape[0]):
+        e = _rel_err(Y[q], ref[q])
+        assert e <= tol, f"power {q + 1}: rel err {e:.3e}"
+
+
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile_nnz,C", [(0, 64 * 1024), (600, 64 * 1024), (128, 8 * 1024), (0, 1 << 30)])
+def test_c1_2d5pt(tile_nnz, C):
+    # 64 x 64 Laplacian, p = 4, natural order (the small configuration)
+    A = W.stencil_2d(64, 5)
+    x = W.uniform_vector(A.n, seed=0)
+    ref = O.spmv_powers(A, x, 4)
+    Y, pl = run_mpk(A, x, 4, C, tile_nnz=tile_nnz)
+    check_powers(Y, ref)
+    Yb, _ = run_mpk(A, x, 4, C, baseline=True, tile_nnz=tile_nnz)
+    check_powers(Yb, ref)
+
+
+@pytest.mark.parametrize("root_mode", [0, 1])
+@pytest.mark.parametrize("p", [1, 4, 8])
+@pytest.mark.parametrize("lanes", [0, 4, 64])
+def test_27pt_random(root_mode, p, lanes):
+    A, _ = W.stencil_27pt_random(24, seed=p + root_mode)
+    x = W.uniform_vector(A.n, seed=p)
+    ref = O.spmv_powers(A, x, p)
+    Y, pl = run_mpk(A, x, p, 2 << 20, root_mode=root_mode, tile_nnz=2000, lanes_per_row=lanes)
+    assert pl.info()["n_tiles"] > 50
+    check_powers(Y, ref)
+
+
+def test_integer_bit_exact():
+    A = W.integer_stencil_27pt(20, seed=5)
+    rng = np.random.default_rng(5)
+    x = rng.integers(-1, 2, size=A.n).astype(np.float64)
+    ref = O.spmv_powers(A, x, 8)
+    Y, _ = run_mpk(A, x, 8, 1 << 20, tile_nnz=3000)
+    assert np.array_equal(Y, ref)
+    Yb, _ = run_mpk(A, x, 8, 1 << 20, baseline=True)
+    assert np.array_equal(Yb, ref)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_irregular_edge_cases(seed):
+    # non-symmetric patterns, empty rows, duplicate entries, disconnected graphs
+    rng = np.random.default_rng(200 + seed)
+    n = [1, 2, 57, 300, 1500][seed]
+    A = W.random_small_csr(n, min(0.5, 3.0 / n), rng, symmetric_pattern=bool(seed % 2),
+                           empty_rows=0.1, duplicates=0.1)
+    x = rng.uniform(-1, 1, size=n)
+    p = [1, 3, 5, 7, 8][seed]
+    ref = O.spmv_powers(A, x, p)
+    Y, _ = run_mpk(A, x, p, 4096, tile_nnz=17, root_mode=seed % 2)
+    check_powers(Y, ref)
+
+
+def test_irregular_generators():
+    for A, p in [(W.random_geometric(20000, 16.0, seed=3)[0], 6),
+                 (W.banded_random(30000, 300, seed=2), 4),
+                 (W.zipf_rows(20000, 1.8, seed=1), 3)]:
+        x = W.uniform_vector(A.n, seed=1)
+        ref = O.spmv_powers(A, x, p)
+        Y, _ = run_mpk(A, x, p, 1 << 20, root_mode=1, tile_nnz=4000)
+        check_powers(Y, ref)
+
+
+def test_spmv_given_order_and_powers():
+    dev = _dev()
+    A, _ = W.stencil_27pt_random(20, seed=7)
+    x = W.uniform_vector(A.n, seed=7)
+    ref = O.spmv_powers(A, x, 3)
+    h = Spmv(A)
+    X = torch.from_numpy(x).to(dev)
+    y = torch.empty_like(X)
+    h.run(X, y)
+    Y = torch.empty((3, A.n), dtype=torch.float64, device=dev)
+    h.powers(3, X, Y)
+    torch.cuda.synchronize()
+    assert _rel_err(y.cpu().numpy(), ref[0]) <= TOL
+    check_powers(Y.cpu().numpy(), ref)
+
+
+def test_permute_round_trip():
+    dev = _dev()
+    A, _ = W.stencil_27pt_random(10, seed=1)
+    pl = Plan(A, 2, 1 << 20, nrhs=4)
+    perm = pl.arrays()[0].astype(np.int64)
+    x = torch.randn(A.n, 4, dtype=torch.float64, device=dev)
+    xp = torch.empty_like(x)
+    back = torch.empty_like(x)
+    pl.permute(x, xp, to_plan=True)
+    pl.permute(xp, back, to_plan=False)
+    torch.cuda.synchronize()
+    assert torch.equal(back, x)
+    assert torch.equal(xp.cpu(), x.cpu()[perm])
+
+
+@pytest.mark.parametrize("k", [2, 4, 8, 16, 32])
+def test_multi_rhs(k):
+    A, _ = W.random_geometric(6000, 16.0, seed=k)
+    X = W.gaussian_block(A.n, k, seed=k)
+    ref = O.spmv_powers(A, X, 6)
+    Y, _ = run_mpk(A, X, 6, 1 << 19, nrhs=k, root_mode=1, tile_nnz=2500)
+    check_powers(Y, ref)
+
+
+@pytest.mark.parametrize("dtype,u", [("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)])
+def test_mixed_precision(dtype, u):
+    # exact on representable integers ...
+    A = W.integer_stencil_27pt(12, seed=3)
+    rng = np.random.default_rng(2)
+    x = rng.integers(-1, 2, size=A.n).astype(np.float64)
+    ref = O.spmv_powers(A, x, 4)
+    Y, _ = run_mpk(A, x, 4, 1 << 20, val_dtype=dtype, tile_nnz=1000)
+    assert np.array_equal(Y, ref)
+    # ... and within the FP32 accumulation bound of the low-precision oracle
+    B, _ = W.stencil_27pt_random(16, seed=4)
+    x = W.uniform_vector(B.n, seed=4)
+    low = O.spmv_powers_lowp(B, x, 4, dtype)
+    absB = W.CSR(B.n, B.rowptr, B.col, np.abs(B.val))
+    bound = O.spmv_powers(absB, np.abs(x), 4)
+    Y, _ = run_mpk(B, x, 4, 1 << 20, val_dtype=dtype, tile_nnz=1000)
+    for q in range(4):
+        # the kernel and the oracle share the rounded matrix; they differ by
+        # FP32 summation order and FMA, (nrow + 2) * 2^-24 per power, grown
+        # through the later powers
+        c = (q + 1) * 31 * 2.0 ** -24
+        assert np.all(np.abs(Y[q] - low[q]) <= c * bound[q])
+
+
+def test_recurrence_chebyshev_blocks():
+    # degree-16 Chebyshev step as two MPK blocks of p = 8 with complex state
+    dev = _dev()
+    A = W.anderson_3d(10, seed=1)
+    x = W.random_phase_state(A.n, seed=1)
+    M, p = 16, 8
+    c = O.cheb_coefficients(M, 4.0)
+    ref = O.cheb_propagate(A, x, c)
+    pl = Plan(A, p, 1 << 20, nrhs=2, tile_nnz=800)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    acc = (c[0].real * X + c[0].imag * torch.stack([-X[:, 1], X[:, 0]], 1)).contiguous()
+    Y = torch.empty((p, A.n, 2), dtype=torch.float64, device=dev)
+    coef = np.stack([c[1:p + 1].real, c[1:p + 1].imag], 1).ravel()
+    alpha = np.array([1.0] + [2.0] * (p - 1))
+    gamma = np.array([0.0] + [-1.0] * (p - 1))
+    pl.run(X, Y, Recurrence(alpha, None, gamma, coef, True, None, acc))
+    # second block: y_{-1} = v_7, y_0 = v_8
+    X2 = Y[p - 1].clone()
+    prev = Y[p - 2].clone()
+    Y2 = torch.empty_like(Y)
+    coef2 = np.stack([c[p + 1:2 * p + 1].real, c[p + 1:2 * p + 1].imag], 1).ravel()
+    pl.run(X2, Y2, Recurrence(np.full(p, 2.0), None, np.full(p, -1.0), coef2, True, prev, acc))
+    pl.status()
+    out = np.empty((A.n, 2))
+    out[perm] = acc.cpu().numpy()
+    assert _rel_err(out, ref) <= 1e-12
+    # the baseline path (p back-to-back SpMV launches) computes the same
+    acc_b = (c[0].real * X + c[0].imag * torch.stack([-X[:, 1], X[:, 0]], 1)).contiguous()
+    Yb = torch.empty_like(Y)
+    pl.run_baseline(X, Yb, Recurrence(alpha, None, gamma, coef, True, None, acc_b))
+    torch.cuda.synchronize()
+    assert torch.allclose(Yb, Y, rtol=1e-13, atol=1e-15)
+
+
+def test_watchdog_path_recovers():
+    # a tiny spin budget may abort a run (the kernel still exits normally);
+    # the plan must report it and stay usable for the next run
+    dev = _dev()
+    A, _ = W.stencil_27pt_random(30, seed=9)
+    x = W.uniform_vector(A.n, seed=9)
+    ref = O.spmv_powers(A, x, 8)
+    pl = Plan(A, 8, 1 << 20, tile_nnz=500, watchdog_spins=1)
+    perm = pl.arrays()[0]
+    X = torch.from_numpy(_to_plan(x, perm)).to(dev)
+    Y = torch.empty((8, A.n), dtype=torch.float64, device=dev)
+    pl.run(X, Y)
+    try:
+        pl.status()
+        check_powers(_unpermute_powers(Y.cpu().numpy(), perm), ref)
+    except MpkError as e:
+        assert e.status == -5
+    # fresh plan with the default watchdog on the same data
+    Y2, _ = run_mpk(A, x, 8, 1 << 20, tile_nnz=500)
+    check_powers(Y2, ref)
+
+
+def test_repeated_runs_reuse_flags():
+    dev = _dev()
+    A, _ = W.stencil_27pt_random(20, seed=11)
+    pl = Plan(A, 6, 1 << 20, tile_nnz=900)
+    perm = pl.arrays()[0]
+    for s in range(4):
+        x = W.uniform_vector(A.n, seed=s)
+        ref = O.spmv_powers(A, x, 6)
+        X = torch.from_numpy(_to_plan(x, perm)).to(dev)
+        Y = torch.empty((6, A.n), dtype=torch.float64, device=dev)
+        pl.run(X, Y)
+        pl.status()
+        check_powers(_unpermute_powers(Y.cpu().numpy(), perm), ref)
+
+
+def test_run_argument_errors():
+    dev = _dev()
+    A = W.stencil_2d(8, 5)
+    pl = Plan(A, 2, 4096, upload=False)
+    X = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    Y = torch.zeros((2, A.n), dtype=torch.float64, device=dev)
+    with pytest.raises(MpkError, match="MPK_ERR_STATE"):
+        pl.run(X, Y)
+    pl.upload()
+    with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+        pl.run(Y[0], Y)  # X inside Y

@@ -1,0 +1,185 @@
+"""Host planner (C++ in libmpk.so, no GPU call) against the oracle: the
+permutation, level pointers, level groups and Lp schedule must match bit for
+bit; the renumbered matrix and the device tile table are checked by their
+invariants."""
+import ctypes
+import re
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2205_01598_amd import MpkError, Plan
+from paper_2205_01598_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _oracle_plan(A, p, C, root_mode=0, f=0.5, bnz=12):
+    perm, lp = O.bfs_levels(A, root_mode)
+    lnnz = O.level_nnz(A, perm, lp)
+    gp = O.level_groups(lnnz, p, C, f, bnz)
+    sch = O.lp_schedule(len(gp) - 1, p)
+    return perm, lp, gp, sch
+
+
+def _check_plan(A, p, C, root_mode=0, f=0.5, dtype="f64", **kw):
+    pl = Plan(A, p, C, upload=False, root_mode=root_mode, safety_factor=f, val_dtype=dtype, **kw)
+    perm, lp, gp, sch = pl.arrays()
+    bnz = {"f64": 12, "f32": 8, "bf16": 6}[dtype]
+    operm, olp, ogp, osch = _oracle_plan(A, p, C, root_mode, f, bnz)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(lp, olp)
+    assert np.array_equal(gp, ogp)
+    assert np.array_equal(sch, osch)
+    # renumbered matrix equals P A P^T
+    rp, col, val = pl.matrix()
+    orp, ocol, oval = O.permute_symmetric(A, operm)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol) and np.array_equal(val, oval)
+    _check_tiles(pl, lp, gp, rp, col)
+    return pl
+
+
+def _check_tiles(pl, lp, gp, rp, col):
+    tr, lo, hi, work = pl.tiles()
+    inf = pl.info()
+    T = inf["n_tiles"]
+    n = inf["n"]
+    p = inf["p"]
+    assert tr[0] == 0 and tr[-1] == n and np.all(np.diff(tr) > 0)
+    group_rows = lp[gp]
+    # tiles never straddle a level-group boundary
+    assert set(group_rows.tolist()) <= set(tr.tolist())
+    tile_group = np.searchsorted(group_rows, tr[:-1], side="right") - 1
+    for t in range(T):
+        r0, r1 = tr[t], tr[t + 1]
+        cols = col[rp[r0]:rp[r1]]
+        need_lo = min(r0, cols.min()) if cols.size else r0
+        need_hi = max(r1 - 1, cols.max()) if cols.size else r1 - 1
+        # dependency range covers every row read (and the tile itself) ...
+        assert tr[lo[t]] <= need_lo and tr[hi[t] + 1] > need_hi
+        # ... and is the tightest such range of tiles
+        assert tr[lo[t] + 1] > need_lo and tr[hi[t]] <= need_hi
+        assert abs(tile_group[lo[t]] - tile_group[t]) <= 1 and abs(tile_group[hi[t]] - tile_group[t]) <= 1
+    # tickets: every (tile, power) once, in Lp diagonal order of the groups,
+    # and every dependency is an earlier ticket
+    tile = work // 64
+    q = work % 64 + 1
+    assert len(work) == T * p
+    assert len(set(zip(tile.tolist(), q.tolist()))) == T * p
+    pos = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(tile, q))}
+    for i, (a, b) in enumerate(zip(tile, q)):
+        if b > 1:
+            assert pos[(int(lo[a]), int(b) - 1)] < i and pos[(int(hi[a]), int(b) - 1)] < i
+
+
+def test_worked_example_plan():
+    A = W.stencil_2d(8, 7)
+    pl = _check_plan(A, 5, 10 ** 6)
+    assert pl.info()["n_levels"] == 15
+
+
+@pytest.mark.parametrize("n,root_mode", [(12, 0), (12, 1), (30, 1)])
+@pytest.mark.parametrize("p,C", [(1, 2 ** 16), (4, 2 ** 20), (8, 3 * 2 ** 20)])
+def test_plan_27pt_random(n, root_mode, p, C):
+    A, _ = W.stencil_27pt_random(n, seed=n)
+    _check_plan(A, p, C, root_mode, tile_nnz=1500)
+
+
+def test_plan_2d5pt_c1():
+    A = W.stencil_2d(64, 5)
+    pl = _check_plan(A, 4, 64 * 1024, tile_nnz=512)
+    assert pl.info()["n_levels"] == 127
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plan_irregular(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 400))
+    A = W.random_small_csr(n, float(rng.uniform(0.001, 0.05)), rng,
+                           symmetric_pattern=bool(seed % 2), empty_rows=0.1, duplicates=0.1)
+    _check_plan(A, int(rng.integers(1, 9)), int(rng.integers(500, 50000)),
+                root_mode=seed % 2, tile_nnz=int(rng.integers(1, 300)))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_plan_dtype_budget(dtype):
+    # Eq. (5) counts b_nz = value bytes + 4 bytes of column index
+    A, _ = W.stencil_27pt_random(16, seed=2)
+    _check_plan(A, 6, 2 ** 20, 1, dtype=dtype)
+
+
+def test_plan_rgg_and_banded():
+    A, _ = W.random_geometric(5000, 12.0, seed=1)
+    _check_plan(A, 6, 2 ** 19, 1, tile_nnz=2000)
+    B = W.banded_random(3000, 40, seed=1)
+    _check_plan(B, 4, 2 ** 18, 0, tile_nnz=700)
+    Z = W.zipf_rows(2000, 2.0, seed=3)
+    _check_plan(Z, 3, 2 ** 18, 0, tile_nnz=900)
+
+
+def test_plan_empty_and_single():
+    Z = W.CSR(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    pl = Plan(Z, 3, 1000, upload=False)
+    assert pl.info()["n_levels"] == 0 and pl.info()["n_tiles"] == 0
+    S = W.CSR(1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([2.0]))
+    pl = _check_plan(S, 3, 1000)
+    assert pl.info()["n_tickets"] == 3
+
+
+def test_plan_rejects_bad_input():
+    A = W.stencil_2d(4, 5)
+    bad_col = W.CSR(A.n, A.rowptr, A.col.copy(), A.val)
+    bad_col.col[3] = A.n
+    with pytest.raises(MpkError, match="MPK_ERR_CSR"):
+        Plan(bad_col, 2, 1000, upload=False)
+    bad_rp = W.CSR(A.n, A.rowptr.copy(), A.col, A.val)
+    bad_rp.rowptr[5], bad_rp.rowptr[6] = bad_rp.rowptr[6], bad_rp.rowptr[5]
+    with pytest.raises(MpkError, match="MPK_ERR_CSR"):
+        Plan(bad_rp, 2, 1000, upload=False)
+    for p in (0, 33):
+        with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+            Plan(A, p, 1000, upload=False)
+    with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+        Plan(A, 2, 0, upload=False)
+    with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+        Plan(A, 2, 1000, upload=False, lanes_per_row=12)
+    with pytest.raises(MpkError, match="MPK_ERR_UNSUPPORTED"):
+        Plan(A, 2, 1000, upload=False, nrhs=4, val_dtype="bf16")
+
+
+@pytest.mark.slow
+def test_plan_c2_full_size():
+    # the 160^3 27-point matrix of the benchmark: plan arrays bit-exact
+    A, _ = W.stencil_27pt_random(160, seed=0)
+    pl = Plan(A, 8, 256 << 20, upload=False, root_mode=1)
+    perm, lp, gp, sch = pl.arrays()
+    operm, olp, ogp, osch = _oracle_plan(A, 8, 256 << 20, 1)
+    assert np.array_equal(perm, operm) and np.array_equal(lp, olp)
+    assert np.array_equal(gp, ogp) and np.array_equal(sch, osch)
+    assert len(lp) - 1 == 160
+
+
+# ----------------------------------------------------------------------------
+# the C-ABI surface
+# ----------------------------------------------------------------------------
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mpk.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b((?:mpk|spmv)_\w+)\s*\(", hdr))
+    L = _lib.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(_lib.SIGNATURES), declared ^ set(_lib.SIGNATURES)
+
+
+def test_abi_struct_sizes():
+    # the ctypes mirrors must match the C layout the library was built with
+    o = _lib.default_options()
+    assert o.size == ctypes.sizeof(_lib.mpk_options)
+    assert o.safety_factor == 0.5 and o.nrhs == 1 and o.val_dtype == 0
+    assert _lib.lib().mpk_status_string(-5).decode() == "device dependency wait timed out"
+    assert _lib.lib().mpk_version().decode().startswith("mpk-gfx950")
