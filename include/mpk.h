@@ -83,7 +83,11 @@ typedef struct mpk_options {
     int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
                                  ((p+1)(b_nz nnz + 8 k rows) < fC); 0 = the paper's form */
-    int32_t reserved[7];
+    int32_t skew;             /* device ticket order over the (group, power) nodes: sorted by
+                                 g + skew*q, then q.  1 (default) = the Lp diagonals of Fig. 6;
+                                 2 puts every dependency a whole diagonal earlier (more work in
+                                 flight without waiting, about twice the reuse window) */
+    int32_t reserved[6];
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */
@@ -149,6 +153,14 @@ void mpk_options_default(mpk_options *opt);
 mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            const mpk_options *opt, mpk_plan **out);
 
+/* Re-derives the level groups, schedule, tiles and tickets for a new p, cache
+ * budget C and options, keeping the BFS levels and the renumbered matrix (the
+ * expensive part of preprocessing; Sec. 5 notes that p_m and C do not change
+ * the levels).  opt->root_mode must equal the plan's.  If the plan was
+ * uploaded its device buffers are rebuilt (synchronous).  On error the plan is
+ * left as it was. */
+mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, const mpk_options *opt);
+
 /* Summary of a plan.  info: host, written on success. */
 mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info);
 
@@ -172,6 +184,13 @@ mpk_status mpk_plan_matrix(const mpk_plan *plan, int64_t *rowptr, int32_t *col, 
  * 64 + (q-1)).  Any pointer may be NULL. */
 mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_lo,
                           int32_t *dep_hi, int32_t *work);
+
+/* Point-to-point dependencies of every tile (host copy), 6 int32 per tile:
+ * (lo, hi) tile ranges, inclusive, in level groups g-1, g and g+1 of the
+ * tile's group g (lo > hi: no dependency there).  Before computing power q a
+ * tile waits for power q-1 of exactly these tiles (Sec. 4.3, with Eq. (4)
+ * limiting the reads of a group to its two neighbour groups). */
+mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges);
 
 /* Allocate the plan's device buffers on the current HIP device and copy the
  * renumbered matrix (converted to val_dtype, round to nearest even) and the

@@ -38,7 +38,7 @@ class mpk_options(ctypes.Structure):
                 ("nrhs", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("tile_nnz", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("skew", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class mpk_plan_info(ctypes.Structure):
@@ -69,10 +69,12 @@ SIGNATURES = {
     "mpk_options_default": (None, [ctypes.POINTER(mpk_options)]),
     "mpk_plan_create": (ctypes.c_int32, [ctypes.POINTER(mpk_csr), ctypes.c_int32, ctypes.c_uint64,
                                          ctypes.POINTER(mpk_options), ctypes.POINTER(_P)]),
+    "mpk_plan_retune": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(mpk_options)]),
     "mpk_plan_query": (ctypes.c_int32, [_P, ctypes.POINTER(mpk_plan_info)]),
     "mpk_plan_arrays": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
     "mpk_plan_matrix": (ctypes.c_int32, [_P, _I64P, _I32P, _F64P]),
     "mpk_plan_tiles": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
+    "mpk_plan_tile_deps": (ctypes.c_int32, [_P, _I32P]),
     "mpk_plan_upload": (ctypes.c_int32, [_P]),
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "mpk_run": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),

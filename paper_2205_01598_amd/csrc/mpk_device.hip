@@ -49,8 +49,9 @@ struct mpk_plan {
     uint64_t device_bytes = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr;
     void *d_val = nullptr;
-    int32_t *d_tile_row = nullptr, *d_dep_lo = nullptr, *d_dep_hi = nullptr, *d_work = nullptr;
+    int32_t *d_tile_row = nullptr, *d_work = nullptr;
     int32_t *d_perm = nullptr;
+    int32_t *d_chunk_row = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
     std::vector<void *> allocs;
 };
@@ -58,14 +59,22 @@ struct mpk_plan {
 struct mpk_spmv {
     int64_t n = 0, nnz = 0;
     int32_t dtype = MPK_F64, nrhs = 1, lanes = 0;
-    int32_t *d_rowptr = nullptr, *d_col = nullptr;
+    int64_t nchunks = 0;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_chunk_row = nullptr;
     void *d_val = nullptr;
     std::vector<void *> allocs;
 };
 
 namespace {
 
-constexpr int kCtrlWords = 16;  // [0] ticket, [1] exit count, [2] error epoch, [3] error ticket
+// control words: [0] arrivals, [1] departures, [2] epoch of a timed-out run,
+// [3] ticket that timed out, then one ticket counter per stripe (256 B apart)
+constexpr int kMaxStripes = 64;
+// s_waitcnt immediate for gfx9-family: vmcnt(0), expcnt and lgkmcnt left at max
+constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kStripeBase = 64;
+constexpr int kStripeStride = 64;
+constexpr int kCtrlWords = kStripeBase + kMaxStripes * kStripeStride;
 
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
@@ -120,25 +129,42 @@ void convert_values(const double *src, size_t n, int32_t dtype, std::vector<uint
 // kernels
 // ----------------------------------------------------------------------------
 
+// Rows of chunks [c0, c1): the chunk kernel for k <= 2, lane groups for k >= 4.
+template <typename VT, int K, int G, bool REC, bool COH>
+__device__ __forceinline__ void chunks_body(int c0, int c1, const int32_t *__restrict__ chunk_row,
+                                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                            const VT *__restrict__ val, const double *__restrict__ x,
+                                            double *__restrict__ y, int q, const double *__restrict__ yq2,
+                                            const RecArgs &rec) {
+    if constexpr (K <= 2) {
+        __shared__ ChunkLds<VT, K> lds;
+        for (int c = c0; c < c1; ++c)
+            chunk_pass<VT, K, REC, COH>(chunk_row[c], chunk_row[c + 1], rowptr, col, val, x, y, q, yq2, rec, lds);
+    } else {
+        rows_pass<VT, K, G, REC, COH>(chunk_row[c0], chunk_row[c1], rowptr, col, val, x, y, q, yq2, rec);
+    }
+}
+
+// Baseline SpMV: one workgroup per chunk.
 template <typename VT, int K, int G, bool REC>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(const int32_t *__restrict__ rowptr,
+__global__ __launch_bounds__(kBlock) void spmv_kernel(const int32_t *__restrict__ chunk_row,
+                                                      const int32_t *__restrict__ rowptr,
                                                       const int32_t *__restrict__ col,
-                                                      const VT *__restrict__ val, int n,
-                                                      int rows_per_block, const double *__restrict__ x,
+                                                      const VT *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y, int q,
                                                       const double *__restrict__ yq2, RecArgs rec) {
-    const int r0 = blockIdx.x * rows_per_block;
-    const int r1 = min(n, r0 + rows_per_block);
-    rows_pass<VT, K, G, REC>(r0, r1, rowptr, col, val, x, y, q, yq2, rec);
+    chunks_body<VT, K, G, REC, false>(blockIdx.x, blockIdx.x + 1, chunk_row, rowptr, col, val, x, y, q, yq2,
+                                      rec);
 }
 
 struct MpkArgs {
+    const int32_t *chunk_row;
+    const int32_t *tile_chunk;
     const int32_t *rowptr;
     const int32_t *col;
     const void *val;
     const int32_t *tile_row;
-    const int32_t *dep_lo;
-    const int32_t *dep_hi;
+    const int32_t *dep3;
     const int32_t *work;
     int32_t n, ntiles, ntickets;
     const double *X;
@@ -146,6 +172,7 @@ struct MpkArgs {
     uint32_t *flags;
     uint32_t *ctrl;
     uint32_t epoch;
+    int32_t nstripes;
     int64_t watchdog;
 };
 
@@ -156,16 +183,21 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Executed by one full wavefront.  Waits until flags[lo..hi] all hold
-// `epoch`; returns false if the watchdog expired or another workgroup already
-// reported a timeout in this run.
-__device__ bool wait_flags(const uint32_t *f, int lo, int hi, const MpkArgs &a, int ticket) {
+// Executed by one full wavefront.  Waits until the flags of the three tile
+// ranges d[0..1], d[2..3], d[4..5] (inclusive, lo > hi = empty) all hold
+// `epoch`, 64 flags per vector load; returns false if the watchdog expired or
+// another workgroup already reported a timeout in this run.
+__device__ bool wait_flags(const uint32_t *f, const int32_t *d, const MpkArgs &a, int ticket) {
     const int lane = threadIdx.x & 63;
+    const int lo0 = d[0], lo1 = d[2], lo2 = d[4];
+    const int n0 = max(0, d[1] - lo0 + 1), n1 = max(0, d[3] - lo1 + 1), n2 = max(0, d[5] - lo2 + 1);
+    const int total = n0 + n1 + n2;
     int64_t spins = 0;
-    for (int base = lo; base <= hi; base += 64) {
-        const int j = base + lane;
+    for (int base = 0; base < total; base += 64) {
+        const int i = base + lane;
+        const int j = i < n0 ? lo0 + i : i < n0 + n1 ? lo1 + (i - n0) : i < total ? lo2 + (i - n0 - n1) : -1;
         for (;;) {
-            const bool ok = (j > hi) || (ld_agent(f + j) == a.epoch);
+            const bool ok = (j < 0) || (ld_agent(f + j) == a.epoch);
             if (__all(ok)) break;
             ++spins;
             if (spins > a.watchdog) {
@@ -183,30 +215,45 @@ __device__ bool wait_flags(const uint32_t *f, int lo, int hi, const MpkArgs &a, 
     return true;
 }
 
+__device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
+    return a.ctrl + kStripeBase + s * kStripeStride;
+}
+
 template <typename VT, int K, int G, bool REC>
 __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec) {
-    __shared__ int s_ticket;
-    __shared__ int s_ok;
+    // Tickets are dealt over `nstripes` counters: stripe s holds tickets
+    // s, s + S, s + 2S, ...  A workgroup joins stripe (arrival index mod S) and
+    // takes that stripe's tickets in increasing order, one at a time.  Every
+    // ticket only waits for earlier tickets and any S running workgroups
+    // cover all stripes, so the smallest unfinished ticket is always held by,
+    // or next for, a running workgroup whose earlier tickets are done: the
+    // grid needs no co-residency.  The last workgroup to leave resets the
+    // counters.
+    __shared__ int s_stripe, s_ok;
+    __shared__ int s_next[2];
+    const int S = a.nstripes;
     const int64_t NK = (int64_t)a.n * K;
     const VT *val = reinterpret_cast<const VT *>(a.val);
-    for (;;) {
-        __syncthreads();  // everyone has read the previous ticket
-        if (threadIdx.x == 0) {
-            const uint32_t t = __hip_atomic_fetch_add(a.ctrl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const bool aborted = ld_agent(a.ctrl + 2) == a.epoch;
-            s_ticket = (aborted || t >= (uint32_t)a.ntickets) ? -1 : (int)t;
-            s_ok = 1;
-        }
-        __syncthreads();
-        const int t = s_ticket;
-        if (t < 0) break;
+    if (threadIdx.x == 0) {
+        const uint32_t arrival = __hip_atomic_fetch_add(a.ctrl + 0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int st = (int)(arrival % (uint32_t)S);
+        const uint32_t k = __hip_atomic_fetch_add(stripe_counter(a, st), 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        s_stripe = st;
+        s_next[0] = (int)min<int64_t>((int64_t)st + (int64_t)k * S, a.ntickets);
+    }
+    __syncthreads();
+    const int stripe = s_stripe;
+    int t = s_next[0];
+    for (int it = 1; t < a.ntickets; ++it) {
         const int w = a.work[t];
         const int tile = w >> 6;
         const int q = (w & 63) + 1;
         if (q > 1) {
+            if (threadIdx.x == 0) s_ok = 1;
+            __syncthreads();
             if (threadIdx.x < 64) {
-                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep_lo[tile],
-                                           a.dep_hi[tile], a, t);
+                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep3 + 6 * tile, a, t);
                 if (!ok && threadIdx.x == 0) s_ok = 0;
             }
             __syncthreads();
@@ -215,18 +262,26 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
-        rows_pass<VT, K, G, REC>(a.tile_row[tile], a.tile_row[tile + 1], a.rowptr, a.col, val, xin, yout,
-                                 q, yq2, rec);
-        // every wavefront makes its stores visible at agent scope before the
-        // workgroup publishes the tile
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        chunks_body<VT, K, G, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk_row, a.rowptr,
+                                         a.col, val, xin, yout, q, yq2, rec);
+        // The next ticket is taken only now: a workgroup never holds a ticket
+        // it is not working on, so no ticket waits behind an idle one.
+        uint32_t kn = 0;
+        if (threadIdx.x == 0)
+            kn = __hip_atomic_fetch_add(stripe_counter(a, stripe), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Release: the tile's results were written with agent-scope stores;
+        // every wavefront waits until its stores have completed (vmcnt = 0)
+        // before the workgroup barrier, after which the flag is published.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        if (threadIdx.x == 0) s_next[it & 1] = (int)min<int64_t>((int64_t)stripe + (int64_t)kn * S, a.ntickets);
         __syncthreads();
         if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, a.epoch);
+        t = s_next[it & 1];
     }
-    // the last workgroup to leave resets the counters for the next run
     if (threadIdx.x == 0) {
         const uint32_t done = __hip_atomic_fetch_add(a.ctrl + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (done == gridDim.x - 1) {
+            for (int st = 0; st < S; ++st) st_agent(stripe_counter(a, st), 0u);
             st_agent(a.ctrl + 0, 0u);
             st_agent(a.ctrl + 1, 0u);
         }
@@ -273,15 +328,16 @@ __global__ __launch_bounds__(kBlock) void bw_probe(const double2 *__restrict__ b
 
 template <typename VT, int K, bool REC>
 struct Dispatch {
-    static hipError_t spmv(int G, int blocks, int rpb, hipStream_t s, const int32_t *rp, const int32_t *ci,
-                           const void *v, int n, const double *x, double *y, int q, const double *yq2,
-                           const RecArgs &rec) {
+    static hipError_t spmv(int G, int blocks, hipStream_t s, const int32_t *chunks, const int32_t *rp,
+                           const int32_t *ci, const void *v, const double *x, double *y, int q,
+                           const double *yq2, const RecArgs &rec) {
+        if constexpr (K <= 2) G = 32;  // the chunk kernel does not use lane groups
         const VT *val = reinterpret_cast<const VT *>(v);
 #define MPK_SPMV_CASE(GG)                                                                              \
     case GG:                                                                                           \
-        if constexpr (GG >= K) {                                                                       \
-            hipLaunchKernelGGL((spmv_kernel<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, rp, ci, \
-                               val, n, rpb, x, y, q, yq2, rec);                                        \
+        if constexpr (GG >= K && (K > 2 || GG == 32)) {                                                \
+            hipLaunchKernelGGL((spmv_kernel<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, chunks, \
+                               rp, ci, val, x, y, q, yq2, rec);                                        \
             return hipGetLastError();                                                                  \
         }                                                                                              \
         break;
@@ -296,10 +352,13 @@ struct Dispatch {
         return hipErrorInvalidValue;
     }
     static hipError_t mpk(int G, int blocks, hipStream_t s, const MpkArgs &a, const RecArgs &rec) {
+        if constexpr (K <= 2) G = 32;
 #define MPK_RUN_CASE(GG)                                                                              \
     case GG:                                                                                          \
-        if constexpr (GG >= K) {                                                                      \
-            hipLaunchKernelGGL((mpk_persistent<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, a, rec); \
+        if constexpr (GG >= K && (K > 2 || GG == 32)) {                                               \
+            MpkArgs a_ = a;                                                                           \
+            a_.nstripes = std::max(1, std::min(blocks, kMaxStripes));                                 \
+            hipLaunchKernelGGL((mpk_persistent<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, a_, rec); \
             return hipGetLastError();                                                                 \
         }                                                                                             \
         break;
@@ -314,12 +373,13 @@ struct Dispatch {
         return hipErrorInvalidValue;
     }
     static const void *mpk_symbol(int G) {
+        if constexpr (K <= 2) G = 32;
         switch (G) {
-            case 4: if constexpr (4 >= K) return (const void *)mpk_persistent<VT, K, 4, REC>; break;
-            case 8: if constexpr (8 >= K) return (const void *)mpk_persistent<VT, K, 8, REC>; break;
-            case 16: if constexpr (16 >= K) return (const void *)mpk_persistent<VT, K, 16, REC>; break;
+            case 4: if constexpr (4 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 4, REC>; break;
+            case 8: if constexpr (8 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 8, REC>; break;
+            case 16: if constexpr (16 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 16, REC>; break;
             case 32: return (const void *)mpk_persistent<VT, K, 32, REC>;
-            case 64: return (const void *)mpk_persistent<VT, K, 64, REC>;
+            case 64: if constexpr (K > 2) return (const void *)mpk_persistent<VT, K, 64, REC>; break;
         }
         return nullptr;
     }
@@ -386,7 +446,6 @@ mpk_status fill_rec(const mpk_recurrence *r, int p, int K, RecArgs &out) {
     return MPK_OK;
 }
 
-int rows_per_block_for(int G) { return (kBlock / G) * 4; }
 
 }  // namespace
 
@@ -405,6 +464,7 @@ void mpk_options_default(mpk_options *opt) {
     opt->val_dtype = MPK_F64;
     opt->nrhs = 1;
     opt->watchdog_spins = 0;
+    opt->skew = 1;
 }
 
 const char *mpk_version(void) { return "mpk-gfx950 0.1"; }
@@ -444,6 +504,36 @@ mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes, co
         return st;
     }
     *out = plan;
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, const mpk_options *opt) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    mpk_options o;
+    mpk_options_default(&o);
+    if (opt) {
+        if (opt->size != sizeof(mpk_options)) return fail(MPK_ERR_ARG, "mpk_options.size mismatch");
+        o = *opt;
+    }
+    if (o.root_mode != plan->hp.opt.root_mode)
+        return fail(MPK_ERR_ARG, "retune keeps the BFS levels: root_mode must not change");
+    if (!supported(o.val_dtype, o.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
+    const bool was_uploaded = plan->uploaded;
+    if (was_uploaded) {
+        HIP_TRY(hipDeviceSynchronize());
+        free_all(plan->allocs);
+        plan->uploaded = false;
+        plan->device_bytes = 0;
+    }
+    HostPlan backup = plan->hp;
+    mpk_status st = build_schedule(plan->hp, p, cache_bytes, o);
+    if (st != MPK_OK) {
+        plan->hp = std::move(backup);
+        if (was_uploaded) (void)mpk_plan_upload(plan);
+        return st;
+    }
+    plan->epoch = 0;
+    if (was_uploaded) return mpk_plan_upload(plan);
     return MPK_OK;
 }
 
@@ -504,6 +594,12 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
     return MPK_OK;
 }
 
+mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    if (ranges) std::copy(plan->hp.dep3.begin(), plan->hp.dep3.end(), ranges);
+    return MPK_OK;
+}
+
 mpk_status mpk_plan_upload(mpk_plan *plan) {
     if (!plan) return fail(MPK_ERR_ARG, "null plan");
     if (plan->uploaded) return MPK_OK;
@@ -530,21 +626,25 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     if ((e = dev_alloc(al, &dv, vbuf.size(), &bytes)) != hipSuccess) return cleanup_fail(e, "val");
     plan->d_val = dv;
     if ((e = dev_alloc(al, &plan->d_tile_row, T + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "tiles");
-    if ((e = dev_alloc(al, &plan->d_dep_lo, T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
-    if ((e = dev_alloc(al, &plan->d_dep_hi, T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_dep3, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_work, W, &bytes)) != hipSuccess) return cleanup_fail(e, "work");
     if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
     if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
     if ((e = dev_alloc(al, &plan->d_perm, h.n, &bytes)) != hipSuccess) return cleanup_fail(e, "perm");
+    if ((e = dev_alloc(al, &plan->d_chunk_row, h.chunk_row.size(), &bytes)) != hipSuccess)
+        return cleanup_fail(e, "chunks");
+    if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
+        return cleanup_fail(e, "chunks");
     struct Cp { void *d; const void *s; size_t b; } cps[] = {
         {plan->d_rowptr, h.rowptr.data(), sizeof(int32_t) * (h.n + 1)},
         {plan->d_col, h.col.data(), sizeof(int32_t) * h.nnz},
         {plan->d_val, vbuf.data(), h.nnz * value_bytes(h.opt.val_dtype)},
         {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
-        {plan->d_dep_lo, h.dep_lo.data(), sizeof(int32_t) * T},
-        {plan->d_dep_hi, h.dep_hi.data(), sizeof(int32_t) * T},
+        {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
         {plan->d_work, h.work.data(), sizeof(int32_t) * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
+        {plan->d_chunk_row, h.chunk_row.data(), sizeof(int32_t) * h.chunk_row.size()},
+        {plan->d_tile_chunk, h.tile_chunk.data(), sizeof(int32_t) * h.tile_chunk.size()},
     };
     for (auto &c : cps)
         if (c.b && (e = hipMemcpy(c.d, c.s, c.b, hipMemcpyHostToDevice)) != hipSuccess)
@@ -612,12 +712,13 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     plan->epoch += 1;
     if (plan->epoch == 0) plan->epoch = 1;
     MpkArgs a;
+    a.chunk_row = plan->d_chunk_row;
+    a.tile_chunk = plan->d_tile_chunk;
     a.rowptr = plan->d_rowptr;
     a.col = plan->d_col;
     a.val = plan->d_val;
     a.tile_row = plan->d_tile_row;
-    a.dep_lo = plan->d_dep_lo;
-    a.dep_hi = plan->d_dep_hi;
+    a.dep3 = plan->d_dep3;
     a.work = plan->d_work;
     a.n = (int32_t)h.n;
     a.ntiles = (int32_t)h.dep_lo.size();
@@ -647,8 +748,7 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
     const int K = h.opt.nrhs, G = h.lanes_per_row;
-    const int rpb = rows_per_block_for(G);
-    const int blocks = (int)((h.n + rpb - 1) / rpb);
+    const int blocks = (int)(h.chunk_row.size() - 1);
     const int64_t NK = h.n * K;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     for (int q = 1; q <= h.p; ++q) {
@@ -656,8 +756,8 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
         hipError_t e = dispatch_all(h.opt.val_dtype, K, rec != nullptr, [&](auto d) {
-            return decltype(d)::spmv(G, blocks, rpb, s, plan->d_rowptr, plan->d_col, plan->d_val, (int)h.n, x,
-                                     y, q, yq2, ra);
+            return decltype(d)::spmv(G, blocks, s, plan->d_chunk_row, plan->d_rowptr, plan->d_col, plan->d_val,
+                                     x, y, q, yq2, ra);
         });
         if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
     }
@@ -709,13 +809,18 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     h->lanes = o.lanes_per_row ? o.lanes_per_row : auto_lanes(mean_row, o.nrhs);
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
+    std::vector<int32_t> chunks;
+    append_chunks(rp, 0, A->n, chunk_nnz_host(o.nrhs), 2048, chunks);
+    chunks.push_back((int32_t)A->n);
+    h->nchunks = (int64_t)chunks.size() - 1;
     std::vector<uint8_t> vbuf;
     convert_values(A->val, A->nnz, o.val_dtype, vbuf);
     hipError_t e;
     uint8_t *dv = nullptr;
     if ((e = dev_alloc(h->allocs, &h->d_rowptr, A->n + 1)) != hipSuccess ||
         (e = dev_alloc(h->allocs, &h->d_col, A->nnz)) != hipSuccess ||
-        (e = dev_alloc(h->allocs, &dv, vbuf.size())) != hipSuccess) {
+        (e = dev_alloc(h->allocs, &dv, vbuf.size())) != hipSuccess ||
+        (e = dev_alloc(h->allocs, &h->d_chunk_row, chunks.size())) != hipSuccess) {
         free_all(h->allocs);
         delete h;
         return fail(e == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP, hipGetErrorString(e));
@@ -726,7 +831,9 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
         (A->nnz && (e = hipMemcpy(h->d_col, A->col, sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice)) !=
                        hipSuccess) ||
         (A->nnz && (e = hipMemcpy(h->d_val, vbuf.data(), A->nnz * value_bytes(o.val_dtype),
-                                  hipMemcpyHostToDevice)) != hipSuccess)) {
+                                  hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(h->d_chunk_row, chunks.data(), sizeof(int32_t) * chunks.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess) {
         free_all(h->allocs);
         delete h;
         return fail(MPK_ERR_HIP, hipGetErrorString(e));
@@ -736,13 +843,11 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
 }
 
 static mpk_status spmv_launch(mpk_spmv *h, const double *x, double *y, hipStream_t s) {
-    const int G = h->lanes, rpb = rows_per_block_for(G);
-    const int blocks = (int)((h->n + rpb - 1) / rpb);
     RecArgs ra;
-    fill_rec(nullptr, 1, h->nrhs, ra);
+    (void)fill_rec(nullptr, 1, h->nrhs, ra);
     hipError_t e = dispatch_all(h->dtype, h->nrhs, false, [&](auto d) {
-        return decltype(d)::spmv(G, blocks, rpb, s, h->d_rowptr, h->d_col, h->d_val, (int)h->n, x, y, 1,
-                                 nullptr, ra);
+        return decltype(d)::spmv(h->lanes, (int)h->nchunks, s, h->d_chunk_row, h->d_rowptr, h->d_col, h->d_val, x,
+                                 y, 1, nullptr, ra);
     });
     if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
     return MPK_OK;

@@ -37,9 +37,12 @@ struct HostPlan {
     // device tiles: row ranges inside level groups
     std::vector<int32_t> tile_row;   // n_tiles+1
     std::vector<int32_t> tile_group; // n_tiles
-    std::vector<int32_t> dep_lo, dep_hi;  // n_tiles
+    std::vector<int32_t> dep_lo, dep_hi;  // n_tiles: all tiles a tile waits for
+    std::vector<int32_t> dep3;       // 6*n_tiles: (lo, hi) in groups g-1, g, g+1 (lo > hi: none)
     std::vector<int32_t> group_tile; // G+1
     std::vector<int32_t> work;       // tickets: tile*64 + (q-1)
+    std::vector<int32_t> chunk_row;  // n_chunks+1: kernel work units inside tiles
+    std::vector<int32_t> tile_chunk; // n_tiles+1
 
     int64_t max_level_rows = 0, max_group_nnz = 0, violating_groups = 0;
     int32_t lanes_per_row = 0;
@@ -51,8 +54,24 @@ struct HostPlan {
 mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            const mpk_options &opt, HostPlan &hp);
 
+// The part of the plan that depends on p, the cache budget and the launch
+// options (level groups, schedule, tiles, dependencies, tickets); reuses the
+// levels and renumbered matrix already in hp.
+mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const mpk_options &opt);
+
 // Validation shared by plan and SpMV creation.
 mpk_status validate_csr(const mpk_csr *A);
+
+// Cuts rows [r0, r1) into chunks of at most max_nnz stored nonzeros and
+// max_rows rows (a longer single row forms its own chunk); appends the start
+// row of every chunk to `out`.
+void append_chunks(const std::vector<int32_t> &rowptr, int64_t r0, int64_t r1, int64_t max_nnz,
+                   int64_t max_rows, std::vector<int32_t> &out);
+void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
+                     std::vector<int32_t> &out);
+
+// Nonzeros per kernel chunk for k right-hand sides (matches the device code).
+int32_t chunk_nnz_host(int32_t k);
 
 // Default lanes-per-row choice for a mean row length and k columns.
 int32_t auto_lanes(double mean_row, int32_t k);

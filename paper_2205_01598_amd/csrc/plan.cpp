@@ -45,6 +45,30 @@ int32_t auto_lanes(double mean_row, int32_t k) {
     return std::min<int32_t>(std::max<int32_t>(g, 4), 64);
 }
 
+int32_t chunk_nnz_host(int32_t k) { return k == 1 ? 2048 : k == 2 ? 1024 : 4096 / k; }
+
+template <typename RP>
+static void append_chunks_t(const RP *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
+                            std::vector<int32_t> &out) {
+    int64_t r = r0;
+    while (r < r1) {
+        out.push_back((int32_t)r);
+        int64_t e = r + 1;
+        while (e < r1 && e - r < max_rows && (int64_t)(rowptr[e + 1] - rowptr[r]) <= max_nnz) ++e;
+        r = e;
+    }
+}
+
+void append_chunks(const std::vector<int32_t> &rowptr, int64_t r0, int64_t r1, int64_t max_nnz,
+                   int64_t max_rows, std::vector<int32_t> &out) {
+    append_chunks_t(rowptr.data(), r0, r1, max_nnz, max_rows, out);
+}
+
+void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
+                     std::vector<int32_t> &out) {
+    append_chunks_t(rowptr, r0, r1, max_nnz, max_rows, out);
+}
+
 mpk_status validate_csr(const mpk_csr *A) {
     if (!A) return fail(MPK_ERR_ARG, "null matrix");
     if (A->n < 0) return fail(MPK_ERR_CSR, "negative n");
@@ -222,56 +246,28 @@ void bfs_levels(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &p
 
 }  // namespace
 
-mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
-                           const mpk_options &opt, HostPlan &hp) {
-    auto t0 = std::chrono::steady_clock::now();
-    mpk_status st = validate_csr(A);
-    if (st != MPK_OK) return st;
+mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const mpk_options &opt) {
     if (p < 1 || p > MPK_MAX_POWER) return fail(MPK_ERR_ARG, "p must be in [1, 32]");
     if (cache_bytes == 0) return fail(MPK_ERR_ARG, "cache budget must be > 0");
     if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
     if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
     if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
-    if (opt.root_mode < 0 || opt.root_mode > 1) return fail(MPK_ERR_ARG, "bad root_mode");
     if (opt.lanes_per_row != 0) {
         int32_t g = opt.lanes_per_row;
         if (g < 4 || g > 64 || (g & (g - 1)) || g < opt.nrhs)
             return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
     }
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
-
-    const int64_t n = A->n;
-    hp.n = n;
-    hp.nnz = A->nnz;
+    if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+    const int64_t n = hp.n;
+    const int64_t L = (int64_t)hp.level_ptr.size() - 1;
+    const int64_t nnz_total = hp.nnz;
     hp.p = p;
     hp.cache_bytes = cache_bytes;
+    const int32_t root_mode = hp.opt.root_mode;
     hp.opt = opt;
-
+    hp.opt.root_mode = root_mode;
     try {
-        // ---- graph, root, levels -------------------------------------------------
-        Graph g;
-        build_graph(A, g);
-        hp.root = 0;
-        if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
-        bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
-        { Graph().adj.swap(g.adj); }
-        hp.iperm.assign(n, 0);
-        for (int64_t i = 0; i < n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
-        const int64_t L = (int64_t)hp.level_ptr.size() - 1;
-
-        // ---- nonzeros per level ------------------------------------------------------
-        hp.level_nnz.assign(L, 0);
-        hp.max_level_rows = 0;
-        for (int64_t l = 0; l < L; ++l) {
-            int64_t s = 0;
-            for (int64_t r = hp.level_ptr[l]; r < hp.level_ptr[l + 1]; ++r) {
-                int64_t o = hp.perm[r];
-                s += A->rowptr[o + 1] - A->rowptr[o];
-            }
-            hp.level_nnz[l] = s;
-            hp.max_level_rows = std::max<int64_t>(hp.max_level_rows, hp.level_ptr[l + 1] - hp.level_ptr[l]);
-        }
-
         // ---- level groups, Eq. (5) ----------------------------------------------------
         const int64_t bnz = bytes_per_nnz(opt.val_dtype);
         const uint64_t budget = (uint64_t)std::floor(opt.safety_factor * (double)cache_bytes);
@@ -315,39 +311,12 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
             }
         }
 
-        // ---- renumbered matrix P A P^T -------------------------------------------------
-        hp.rowptr.assign(n + 1, 0);
-        for (int64_t r = 0; r < n; ++r) {
-            int64_t o = hp.perm[r];
-            hp.rowptr[r + 1] = hp.rowptr[r] + (int32_t)(A->rowptr[o + 1] - A->rowptr[o]);
-        }
-        hp.col.resize(A->nnz);
-        hp.val.resize(A->nnz);
-#pragma omp parallel
-        {
-            std::vector<std::pair<int32_t, double>> buf;
-#pragma omp for schedule(dynamic, 2048)
-            for (int64_t r = 0; r < n; ++r) {
-                int64_t o = hp.perm[r];
-                int64_t a = A->rowptr[o], b = A->rowptr[o + 1];
-                buf.resize(b - a);
-                for (int64_t j = a; j < b; ++j) buf[j - a] = {hp.iperm[A->col[j]], A->val[j]};
-                std::stable_sort(buf.begin(), buf.end(),
-                                 [](const auto &x, const auto &y) { return x.first < y.first; });
-                int64_t out = hp.rowptr[r];
-                for (size_t t = 0; t < buf.size(); ++t) {
-                    hp.col[out + t] = buf[t].first;
-                    hp.val[out + t] = buf[t].second;
-                }
-            }
-        }
-
         // ---- device tiles --------------------------------------------------------------
         int64_t tile_nnz = opt.tile_nnz;
         if (tile_nnz <= 0) tile_nnz = 32768;
         const int64_t max_tile_rows = 1 << 14;
         hp.tile_nnz = (int32_t)tile_nnz;
-        double mean_row = n > 0 ? (double)A->nnz / (double)n : 1.0;
+        double mean_row = n > 0 ? (double)nnz_total / (double)n : 1.0;
         hp.lanes_per_row = opt.lanes_per_row ? opt.lanes_per_row : auto_lanes(mean_row, opt.nrhs);
         hp.tile_row.clear();
         hp.tile_group.clear();
@@ -381,43 +350,178 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
         hp.tile_row.push_back((int32_t)n);
         const int64_t T = (int64_t)hp.tile_group.size();
 
-        // dependency range of each tile: every tile holding a column its rows
-        // read, plus the tile itself (its own rows at power q-1)
+        // Point-to-point dependencies of each tile (Sec. 4.3).  By Eq. (4) a
+        // tile of group g only reads rows of groups g-1, g and g+1.  For each
+        // of the three groups the tile waits for the tiles spanning the
+        // smallest and largest column it reads there; in its own group the
+        // range also covers the tile itself.  dep_lo/dep_hi is the union.
         hp.dep_lo.assign(T, 0);
         hp.dep_hi.assign(T, 0);
+        hp.dep3.assign(6 * T, 0);
         bool bad = false;
+        auto tile_of = [&](int64_t row) -> int64_t {
+            return std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)row) - hp.tile_row.begin() - 1;
+        };
 #pragma omp parallel for schedule(dynamic, 16) reduction(|| : bad)
         for (int64_t t = 0; t < T; ++t) {
-            int64_t r0 = hp.tile_row[t], r1 = hp.tile_row[t + 1];
-            int64_t lo = r0, hi = r1 - 1;
-            for (int64_t j = hp.rowptr[r0]; j < hp.rowptr[r1]; ++j) {
-                lo = std::min<int64_t>(lo, hp.col[j]);
-                hi = std::max<int64_t>(hi, hp.col[j]);
+            const int64_t gi = hp.tile_group[t];
+            const int64_t r0 = hp.tile_row[t], r1 = hp.tile_row[t + 1];
+            int64_t lo[3], hi[3], gstart[3], gend[3];
+            for (int m = 0; m < 3; ++m) {
+                const int64_t gm = gi - 1 + m;
+                lo[m] = std::numeric_limits<int64_t>::max();
+                hi[m] = -1;
+                gstart[m] = (gm >= 0 && gm < G) ? hp.level_ptr[hp.group_ptr[gm]] : 0;
+                gend[m] = (gm >= 0 && gm < G) ? hp.level_ptr[hp.group_ptr[gm + 1]] : 0;
             }
-            int64_t tl = std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)lo) -
-                         hp.tile_row.begin() - 1;
-            int64_t th = std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)hi) -
-                         hp.tile_row.begin() - 1;
-            hp.dep_lo[t] = (int32_t)tl;
-            hp.dep_hi[t] = (int32_t)th;
-            // Eq. (4): a level only touches its neighbour levels, so a tile
-            // only depends on tiles of its own and the two adjacent groups
-            int64_t gi = hp.tile_group[t];
-            if (hp.tile_group[tl] < gi - 1 || hp.tile_group[th] > gi + 1) bad = true;
+            lo[1] = r0;
+            hi[1] = r1 - 1;
+            for (int64_t j = hp.rowptr[r0]; j < hp.rowptr[r1]; ++j) {
+                const int64_t c = hp.col[j];
+                int m = -1;
+                for (int mm = 0; mm < 3; ++mm)
+                    if (c >= gstart[mm] && c < gend[mm]) m = mm;
+                if (m < 0) {
+                    bad = true;
+                    continue;
+                }
+                lo[m] = std::min(lo[m], c);
+                hi[m] = std::max(hi[m], c);
+            }
+            int64_t all_lo = std::numeric_limits<int64_t>::max(), all_hi = -1;
+            for (int m = 0; m < 3; ++m) {
+                if (hi[m] < 0) {
+                    hp.dep3[6 * t + 2 * m] = 1;
+                    hp.dep3[6 * t + 2 * m + 1] = 0;
+                    continue;
+                }
+                const int64_t tl = tile_of(lo[m]), th = tile_of(hi[m]);
+                hp.dep3[6 * t + 2 * m] = (int32_t)tl;
+                hp.dep3[6 * t + 2 * m + 1] = (int32_t)th;
+                all_lo = std::min(all_lo, tl);
+                all_hi = std::max(all_hi, th);
+            }
+            hp.dep_lo[t] = (int32_t)all_lo;
+            hp.dep_hi[t] = (int32_t)all_hi;
         }
         if (bad) return fail(MPK_ERR_CSR, "internal: tile dependency crosses more than one level group");
 
-        // tickets in Lp diagonal order, tiles of a node in row order
+        // kernel chunks inside every tile
+        hp.chunk_row.clear();
+        hp.tile_chunk.assign(T + 1, 0);
+        const int64_t cnz = chunk_nnz_host(opt.nrhs);
+        for (int64_t t = 0; t < T; ++t) {
+            hp.tile_chunk[t] = (int32_t)hp.chunk_row.size();
+            append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, 2048, hp.chunk_row);
+        }
+        hp.tile_chunk[T] = (int32_t)hp.chunk_row.size();
+        hp.chunk_row.push_back((int32_t)n);
+
+        // Tickets: the (group, power) nodes in the order of key g + skew*q,
+        // ties by q (skew 1 is exactly the Lp diagonal order of Fig. 6), tiles
+        // of a node in row order.  For any skew >= 1 the dependencies of a
+        // node, (g-1..g+1, q-1), have a smaller key or, at skew 1, the same
+        // key and a smaller q, so every ticket only waits for earlier ones.
+        std::vector<std::pair<int64_t, int64_t>> nodes;  // (key * (p+1) + q, g)
+        nodes.reserve(G * p);
+        for (int64_t gi = 0; gi < G; ++gi)
+            for (int64_t q = 1; q <= p; ++q) nodes.push_back({(gi + opt.skew * q) * (p + 1) + q, gi});
+        std::sort(nodes.begin(), nodes.end());
         hp.work.clear();
         hp.work.reserve(T * p);
-        for (size_t s = 0; s < hp.schedule.size(); s += 3) {
-            int32_t q = hp.schedule[s + 1], gi = hp.schedule[s + 2];
-            for (int32_t t = hp.group_tile[gi]; t < hp.group_tile[gi + 1]; ++t)
-                hp.work.push_back(t * 64 + (q - 1));
+        for (const auto &nd : nodes) {
+            const int32_t q = (int32_t)(nd.first % (p + 1)), gi = (int32_t)nd.second;
+            for (int32_t t = hp.group_tile[gi]; t < hp.group_tile[gi + 1]; ++t) hp.work.push_back(t * 64 + (q - 1));
         }
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");
     }
+    return MPK_OK;
+}
+
+mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
+                           const mpk_options &opt, HostPlan &hp) {
+    auto t0 = std::chrono::steady_clock::now();
+    mpk_status st = validate_csr(A);
+    if (st != MPK_OK) return st;
+    if (p < 1 || p > MPK_MAX_POWER) return fail(MPK_ERR_ARG, "p must be in [1, 32]");
+    if (cache_bytes == 0) return fail(MPK_ERR_ARG, "cache budget must be > 0");
+    if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
+    if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
+    if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
+    if (opt.root_mode < 0 || opt.root_mode > 1) return fail(MPK_ERR_ARG, "bad root_mode");
+    if (opt.lanes_per_row != 0) {
+        int32_t g = opt.lanes_per_row;
+        if (g < 4 || g > 64 || (g & (g - 1)) || g < opt.nrhs)
+            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
+    }
+    if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
+    if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+
+    const int64_t n = A->n;
+    hp.n = n;
+    hp.nnz = A->nnz;
+    hp.p = p;
+    hp.cache_bytes = cache_bytes;
+    hp.opt = opt;
+
+    try {
+        // ---- graph, root, levels -------------------------------------------------
+        Graph g;
+        build_graph(A, g);
+        hp.root = 0;
+        if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
+        bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+        { Graph().adj.swap(g.adj); }
+        hp.iperm.assign(n, 0);
+        for (int64_t i = 0; i < n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
+        const int64_t L = (int64_t)hp.level_ptr.size() - 1;
+
+        // ---- nonzeros per level ------------------------------------------------------
+        hp.level_nnz.assign(L, 0);
+        hp.max_level_rows = 0;
+        for (int64_t l = 0; l < L; ++l) {
+            int64_t s = 0;
+            for (int64_t r = hp.level_ptr[l]; r < hp.level_ptr[l + 1]; ++r) {
+                int64_t o = hp.perm[r];
+                s += A->rowptr[o + 1] - A->rowptr[o];
+            }
+            hp.level_nnz[l] = s;
+            hp.max_level_rows = std::max<int64_t>(hp.max_level_rows, hp.level_ptr[l + 1] - hp.level_ptr[l]);
+        }
+
+        // ---- renumbered matrix P A P^T -------------------------------------------------
+        hp.rowptr.assign(n + 1, 0);
+        for (int64_t r = 0; r < n; ++r) {
+            int64_t o = hp.perm[r];
+            hp.rowptr[r + 1] = hp.rowptr[r] + (int32_t)(A->rowptr[o + 1] - A->rowptr[o]);
+        }
+        hp.col.resize(A->nnz);
+        hp.val.resize(A->nnz);
+#pragma omp parallel
+        {
+            std::vector<std::pair<int32_t, double>> buf;
+#pragma omp for schedule(dynamic, 2048)
+            for (int64_t r = 0; r < n; ++r) {
+                int64_t o = hp.perm[r];
+                int64_t a = A->rowptr[o], b = A->rowptr[o + 1];
+                buf.resize(b - a);
+                for (int64_t j = a; j < b; ++j) buf[j - a] = {hp.iperm[A->col[j]], A->val[j]};
+                std::stable_sort(buf.begin(), buf.end(),
+                                 [](const auto &x, const auto &y) { return x.first < y.first; });
+                int64_t out = hp.rowptr[r];
+                for (size_t t = 0; t < buf.size(); ++t) {
+                    hp.col[out + t] = buf[t].first;
+                    hp.val[out + t] = buf[t].second;
+                }
+            }
+        }
+
+    } catch (const std::bad_alloc &) {
+        return fail(MPK_ERR_OOM, "host allocation failed while planning");
+    }
+    st = build_schedule(hp, p, cache_bytes, opt);
+    if (st != MPK_OK) return st;
     hp.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return MPK_OK;
 }

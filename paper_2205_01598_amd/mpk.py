@@ -91,6 +91,14 @@ class Plan:
     def upload(self):
         check(lib().mpk_plan_upload(self._h))
 
+    def retune(self, p: int, cache_bytes: int, **opts):
+        """New p / cache budget / launch options on the same BFS levels."""
+        o = default_options(**opts)
+        check(lib().mpk_plan_retune(self._h, int(p), int(cache_bytes), ctypes.byref(o)))
+        self.p = int(p)
+        self.nrhs = int(o.nrhs)
+        return self
+
     def info(self) -> dict:
         i = _lib.mpk_plan_info()
         check(lib().mpk_plan_query(self._h, ctypes.byref(i)))
@@ -127,6 +135,12 @@ class Plan:
         check(lib().mpk_plan_tiles(self._h, tr.ctypes.data_as(P), lo.ctypes.data_as(P),
                                    hi.ctypes.data_as(P), work.ctypes.data_as(P)))
         return tr, lo, hi, work
+
+    def tile_deps(self):
+        T = self.info()["n_tiles"]
+        d = np.empty(6 * T, np.int32)
+        check(lib().mpk_plan_tile_deps(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return d.reshape(T, 6)
 
     # -- device calls ------------------------------------------------------------
     def permute(self, x, out, to_plan: bool, stream=None):

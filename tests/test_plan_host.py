@@ -63,6 +63,26 @@ def _check_tiles(pl, lp, gp, rp, col):
         # ... and is the tightest such range of tiles
         assert tr[lo[t] + 1] > need_lo and tr[hi[t]] <= need_hi
         assert abs(tile_group[lo[t]] - tile_group[t]) <= 1 and abs(tile_group[hi[t]] - tile_group[t]) <= 1
+    # three point-to-point ranges: every column read (and the tile itself)
+    # lies in a listed tile, each range stays inside its group, and the
+    # bounds are the tiles of the extreme columns read in that group
+    d3 = pl.tile_deps()
+    for t in range(T):
+        g = tile_group[t]
+        r0, r1 = tr[t], tr[t + 1]
+        cols = np.concatenate([col[rp[r0]:rp[r1]], np.arange(r0, r1)])
+        ctile = np.searchsorted(tr, cols, side="right") - 1
+        covered = np.zeros(len(cols), bool)
+        for m in range(3):
+            a, b = d3[t, 2 * m], d3[t, 2 * m + 1]
+            if a > b:
+                assert not np.any(tile_group[ctile] == g - 1 + m)
+                continue
+            assert tile_group[a] == g - 1 + m and tile_group[b] == g - 1 + m
+            sel = tile_group[ctile] == g - 1 + m
+            assert ctile[sel].min() == a and ctile[sel].max() == b
+            covered |= (ctile >= a) & (ctile <= b)
+        assert covered.all()
     # tickets: every (tile, power) once, in Lp diagonal order of the groups,
     # and every dependency is an earlier ticket
     tile = work // 64
@@ -86,6 +106,44 @@ def test_worked_example_plan():
 def test_plan_27pt_random(n, root_mode, p, C):
     A, _ = W.stencil_27pt_random(n, seed=n)
     _check_plan(A, p, C, root_mode, tile_nnz=1500)
+
+
+@pytest.mark.parametrize("skew", [1, 2, 3])
+def test_plan_skew_orders(skew):
+    # skew 1 reproduces the Lp diagonal order of the schedule; any skew keeps
+    # every dependency an earlier ticket
+    A, _ = W.stencil_27pt_random(14, seed=5)
+    pl = _check_plan(A, 5, 2 ** 19, 1, tile_nnz=3000, skew=skew)
+    _, _, gp, sch = pl.arrays()
+    tr, lo, hi, work = pl.tiles()
+    group_rows = pl.arrays()[1][gp]
+    tile_group = np.searchsorted(group_rows, tr[:-1], side="right") - 1
+    nodes = []
+    for w in work:
+        node = (int(tile_group[w // 64]), int(w % 64 + 1))
+        if not nodes or nodes[-1] != node:
+            nodes.append(node)
+    if skew == 1:
+        assert nodes == [(int(i), int(q)) for d, q, i in sch]
+    keys = [g + skew * q for g, q in nodes]
+    assert keys == sorted(keys)
+
+
+def test_retune_matches_fresh_plan():
+    # retune keeps the levels; groups, schedule and tiles equal a fresh plan
+    A, _ = W.stencil_27pt_random(16, seed=8)
+    pl = Plan(A, 4, 2 ** 20, upload=False, root_mode=1, tile_nnz=2000)
+    for p, C, kw in [(8, 3 * 2 ** 19, {}), (2, 2 ** 18, {"tile_nnz": 700, "skew": 2}),
+                     (6, 2 ** 21, {"val_dtype": "bf16"})]:
+        pl.retune(p, C, root_mode=1, **kw)
+        fresh = Plan(A, p, C, upload=False, root_mode=1, **kw)
+        for a, b in zip(pl.arrays(), fresh.arrays()):
+            assert np.array_equal(a, b)
+        for a, b in zip(pl.tiles(), fresh.tiles()):
+            assert np.array_equal(a, b)
+        assert np.array_equal(pl.tile_deps(), fresh.tile_deps())
+    with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+        pl.retune(4, 2 ** 20, root_mode=0)
 
 
 def test_plan_2d5pt_c1():
