@@ -128,6 +128,13 @@ def main():
     plan.retune(p, cfg["cache"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile"])
     info = plan.info()
 
+    # ---- calibration copy for the HBM counters: 256 MiB read + 256 MiB written ---------
+    calib_src = torch.empty(32 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src, calib_dst
+
     # ---- timed region: exactly `steps` MPK runs ------------------------------------
     torch.cuda.synchronize()
     ms = timed(torch, lambda: plan.run(X, Y), args.steps, args.warmup)

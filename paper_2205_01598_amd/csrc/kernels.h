@@ -197,28 +197,43 @@ __device__ __forceinline__ void chunk_pass(int r0, int r1, const int32_t *__rest
     const int tid = threadIdx.x;
     const int j0 = rowptr[r0], j1 = rowptr[r1];
     if (j1 - j0 <= chunk_nnz(K)) {
-        // phase 1: products of the chunk's nonzeros, many independent loads per thread
+        if (j1 == j0) {  // rows without stored entries: y = 0 (uniform branch)
+            for (int r = r0 + tid; r < r1; r += kBlock) {
+                double v[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) v[c] = 0.0;
+                store_row<K, REC, COH>(r, v, x, y, q, yq2, rec);
+            }
+            return;
+        }
+        // phase 1: products of the chunk's nonzeros.  Every load is
+        // unconditional (slots past the chunk re-read its last entry, whose
+        // product phase 2 never reads), so a thread issues all its val/col
+        // loads, then all its gathers, without waiting in between.
         int cj[NPT];
         AT a[NPT];
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
-            const int j = j0 + tid + m * kBlock;
-            const bool in = j < j1;
-            cj[m] = in ? col[j] : 0;
-            a[m] = in ? (AT)load_value(val, j) : (AT)0;
+            const int jc = min(j0 + tid + m * kBlock, j1 - 1);
+            cj[m] = col[jc];
+            a[m] = (AT)load_value(val, jc);
         }
+        // row bounds of the thread's first phase-2 row, fetched early
+        const int rf = min(r0 + tid, r1);
+        const int rs0 = rowptr[rf], re0 = rowptr[min(rf + 1, r1)];
+        AT xv[NPT][K];
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
+        for (int m = 0; m < NPT; ++m)
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                const AT xv = (AT)x[(int64_t)cj[m] * K + c];
-                lds.prod[(tid + m * kBlock) * K + c] = a[m] * xv;
-            }
-        }
+            for (int c = 0; c < K; ++c) xv[m][c] = (AT)x[(int64_t)cj[m] * K + c];
+#pragma unroll
+        for (int m = 0; m < NPT; ++m)
+#pragma unroll
+            for (int c = 0; c < K; ++c) lds.prod[(tid + m * kBlock) * K + c] = a[m] * xv[m][c];
         __syncthreads();
         // phase 2: one thread per row sums its products in stored order
         for (int r = r0 + tid; r < r1; r += kBlock) {
-            const int s = rowptr[r] - j0, e = rowptr[r + 1] - j0;
+            const int s = (r == rf ? rs0 : rowptr[r]) - j0, e = (r == rf ? re0 : rowptr[r + 1]) - j0;
             AT sum[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) sum[c] = (AT)0;
