@@ -30,6 +30,36 @@ METRIC = "MPK GFLOP/s & speedup vs p× SpMV (same GPU), FP64 and mixed precision
 HBM_PEAK_GBS = 8000.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "mpk_persistent_27pt160_p8.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.h", "mpk_device.hip"):
+        with open(os.path.join(ROOT, "paper_2205_01598_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM-side bytes per launch from the committed counter summary, if it was
+    taken on the kernel sources as they are now (else None)."""
+    try:
+        kv = {}
+        with open(PROFILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -62,6 +92,109 @@ def rel_errs(Y, ref):
     return [float(np.linalg.norm(Y[q] - ref[q]) / np.linalg.norm(ref[q])) for q in range(ref.shape[0])]
 
 
+def bench_small_2d(torch, Plan, W, dev):
+    """64 x 64 5-point Laplacian, p = 4 (cache- and launch-latency-bound)."""
+    A = W.stencil_2d(64, 5)
+    x = W.uniform_vector(A.n, seed=0)
+    pl = Plan(A, 4, 64 * 1024, root_mode=1, tile_nnz=2048)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    Y = torch.empty((4, A.n), dtype=torch.float64, device=dev)
+    tb = timed(torch, lambda: pl.run_baseline(X, Y), 200, 20)
+    tm = timed(torch, lambda: pl.run(X, Y), 200, 20)
+    pl.status()
+    return {"workload": "5-point Laplacian 64^2, p=4", "mpk_us": round(tm * 1e3, 2),
+            "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3)}
+
+
+def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
+    """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8."""
+    from paper_2205_01598_amd.cheb import ChebPropagator
+
+    A = W.anderson_3d(128, seed=0)
+    x = W.random_phase_state(A.n, seed=0)
+    M, p, r_dt = 32, 8, 10.0
+    out = {"workload": "Anderson 128^3 (W=16, open BC, A=H/14), degree 32, p=8, r*dt=10, complex state"}
+    ref = None
+    try:
+        import oracle as O
+
+        c = O.cheb_coefficients(M, r_dt)
+        ref = [x]
+        for _ in range(steps_err):
+            ref.append(O.cheb_propagate(A, ref[-1], c))
+    except ImportError:
+        pass
+    for dt in ("f64", "f32", "bf16"):
+        pl = Plan(A, p, 256 << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=2, tile_nnz=8192)
+        perm = pl.arrays()[0].astype(np.int64)
+        prop = ChebPropagator(pl, M, r_dt)
+        X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+        acc = torch.empty_like(X)
+        tm = timed(torch, lambda: prop.step(X, acc), 20, 3)
+        tb = timed(torch, lambda: prop.step(X, acc, baseline=True), 20, 3)
+        pl.status()
+        ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
+               "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1)}
+        if ref is not None:
+            errs, state = [], X
+            for s_ in range(steps_err):
+                nxt = torch.empty_like(state)
+                prop.step(state, nxt)
+                h = np.empty((A.n, 2))
+                h[perm] = nxt.cpu().numpy()
+                errs.append(float(f"{np.linalg.norm(h - ref[s_ + 1]) / np.linalg.norm(ref[s_ + 1]):.3e}"))
+                state = nxt
+            ent["rel_err_per_step"] = errs
+            ent["norm_after_steps"] = float(f"{np.linalg.norm(h):.12f}")
+        out[dt] = ent
+        del pl, prop
+    return out
+
+
+def bench_multi_rhs(torch, Plan, W, dev):
+    """Random geometric graph, N = 2M, ~16 nnz/row, p = 6, k = 4..32."""
+    A, _ = W.random_geometric(2_000_000, 16.0, seed=0)
+    out = {"workload": f"random geometric graph N=2M nnz={A.nnz}, row-normalised, p=6"}
+    pl = Plan(A, 6, 256 << 20, root_mode=1)
+    perm = pl.arrays()[0].astype(np.int64)
+    for k in (4, 8, 16, 32):
+        Xh = W.gaussian_block(A.n, k, seed=k)
+        X = torch.from_numpy(np.ascontiguousarray(Xh[perm])).to(dev)
+        Y = torch.empty((6, A.n, k), dtype=torch.float64, device=dev)
+        pl.retune(6, 256 << 20, root_mode=1, nrhs=k)
+        tb = timed(torch, lambda: pl.run_baseline(X, Y), 5, 2)
+        best = None
+        for skew, tile in ((1, 2048), (2, 2048), (2, 8192)):
+            pl.retune(6, 256 << 20, root_mode=1, nrhs=k, skew=skew, tile_nnz=tile)
+            t = timed(torch, lambda: pl.run(X, Y), 5, 2)
+            if best is None or t < best[0]:
+                best = (t, {"skew": skew, "tile_nnz": tile})
+        pl.status()
+        out[f"k{k}"] = {"mpk_ms": round(best[0], 4), "baseline_ms": round(tb, 4), "speedup": round(tb / best[0], 3),
+                        "gflops": round(2.0 * A.nnz * 6 * k / best[0] / 1e6, 1), "config": best[1]}
+        del X, Y
+    return out
+
+
+def probe():
+    """Load-only read bandwidth versus footprint: L2 (4 MB per XCD), the
+    256 MB Infinity Cache and HBM (the analog of the paper's Fig. 1)."""
+    import torch
+
+    from paper_2205_01598_amd import bw_probe
+
+    dev = torch.device("cuda:0")
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device=dev).fill_(1)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    print("footprint_MB  GB/s(one pass per launch, 8192 WGs)  GB/s(each WG re-reads its share 16x, 2048 WGs)")
+    for mb in (8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 512, 1024, 2048, 4096):
+        b = buf[: mb << 20]
+        t1 = timed(torch, lambda: bw_probe(b, 1, 8192, sink), 20, 3)
+        t2 = timed(torch, lambda: bw_probe(b, 16, 2048, sink), 5, 1)
+        print(f"{mb:8d}  {mb * (1 << 20) / t1 / 1e6:12.1f}  {16 * mb * (1 << 20) / t2 / 1e6:12.1f}", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +206,15 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the tuning sweep")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (2D 64^2, Chebyshev Anderson 128^3, multi-RHS RGG)")
+    ap.add_argument("--only-main", action="store_true", help="only the headline p (no p=4/6)")
+    ap.add_argument("--probe", action="store_true",
+                    help="load-only bandwidth versus footprint (one full pass per launch) and exit")
     args = ap.parse_args()
+    if args.probe:
+        probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -148,7 +289,7 @@ def main():
 
     # ---- other powers ----------------------------------------------------------------
     other = {}
-    for q in (4, 6):
+    for q in (() if args.only_main else (4, 6)):
         if q == p:
             continue
         Yq = torch.empty((q, n), dtype=torch.float64, device=dev)
@@ -198,6 +339,16 @@ def main():
             mixed[dt] = ent
             del pm
 
+    extra = {}
+    if not args.no_extra:
+        del plan
+        extra["small_2d"] = bench_small_2d(torch, Plan, W, dev)
+        log(f"small 2D: {extra['small_2d']}")
+        extra["chebyshev"] = bench_chebyshev(torch, Plan, W, dev)
+        log(f"chebyshev: {extra['chebyshev']}")
+        extra["multi_rhs"] = bench_multi_rhs(torch, Plan, W, dev)
+        log(f"multi-RHS: {extra['multi_rhs']}")
+
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
@@ -224,9 +375,10 @@ def main():
         "other_powers": other,
         "mixed_precision": mixed,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                      "kernel": "mpk_persistent", "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
+        "other_workloads": extra,
     }
     if ref is not None:
         out["fp64_max_rel_err"] = float(f"{max(rel_errs(Yh, ref)):.3e}")

@@ -79,7 +79,7 @@ typedef struct mpk_options {
     int32_t nrhs;             /* k, right-hand sides per run, 1..MPK_MAX_NRHS (default 1) */
     int32_t workgroups;       /* persistent-kernel grid size; 0 = automatic */
     int32_t tile_nnz;         /* target nonzeros per device tile; 0 = automatic */
-    int32_t lanes_per_row;    /* lanes cooperating on one row: 4..64 (power of 2, >= k); 0 = auto */
+    int32_t reserved0;        /* must be 0 */
     int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
                                  ((p+1)(b_nz nnz + 8 k rows) < fC); 0 = the paper's form */
@@ -87,7 +87,11 @@ typedef struct mpk_options {
                                  g + skew*q, then q.  1 (default) = the Lp diagonals of Fig. 6;
                                  2 puts every dependency a whole diagonal earlier (more work in
                                  flight without waiting, about twice the reuse window) */
-    int32_t reserved[6];
+    int32_t xcd_streams;      /* 1 (default): one ticket sequence for the whole grid.  8: the tiles
+                                 of every level group are cut into 8 slices and slice s is run by
+                                 workgroups with blockIdx % 8 == s (the XCD they are dispatched to
+                                 on MI355X), so a tile meets the same L2 at every power */
+    int32_t reserved[5];
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */
@@ -104,7 +108,7 @@ typedef struct mpk_plan_info {
     int64_t violating_groups; /* groups that break Eq. (5) (single bulky levels) */
     uint64_t device_bytes;    /* device memory held after mpk_plan_upload */
     int32_t workgroups;       /* grid size mpk_run will launch */
-    int32_t lanes_per_row;
+    int32_t n_chunks;         /* kernel work units (<= chunk_nnz(k) nonzeros each) */
     int32_t tile_nnz;
     int32_t val_dtype;
     double plan_seconds;      /* host time spent in mpk_plan_create */

@@ -36,9 +36,10 @@ class mpk_options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("safety_factor", ctypes.c_double),
                 ("root_mode", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("tile_nnz", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+                ("tile_nnz", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
-                ("skew", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("skew", ctypes.c_int32), ("xcd_streams", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class mpk_plan_info(ctypes.Structure):
@@ -47,7 +48,7 @@ class mpk_plan_info(ctypes.Structure):
                 ("n_tiles", ctypes.c_int64), ("n_tickets", ctypes.c_int64), ("root", ctypes.c_int64),
                 ("max_level_rows", ctypes.c_int64), ("max_group_nnz", ctypes.c_int64),
                 ("violating_groups", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
-                ("workgroups", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("tile_nnz", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
                 ("plan_seconds", ctypes.c_double)]
 

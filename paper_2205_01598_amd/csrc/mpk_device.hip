@@ -58,7 +58,7 @@ struct mpk_plan {
 
 struct mpk_spmv {
     int64_t n = 0, nnz = 0;
-    int32_t dtype = MPK_F64, nrhs = 1, lanes = 0;
+    int32_t dtype = MPK_F64, nrhs = 1;
     int64_t nchunks = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_chunk_row = nullptr;
     void *d_val = nullptr;
@@ -67,9 +67,12 @@ struct mpk_spmv {
 
 namespace {
 
-// control words: [0] arrivals, [1] departures, [2] epoch of a timed-out run,
-// [3] ticket that timed out, then one ticket counter per stripe (256 B apart)
+// control words: [1] departures, [2] epoch of a timed-out run, [3] ticket
+// that timed out, [16..23] arrivals per stream, then one ticket counter per
+// (stream, sub-stripe) pair, 256 B apart
 constexpr int kMaxStripes = 64;
+constexpr int kMaxStreams = 8;
+constexpr int kArrivalBase = 16;
 // s_waitcnt immediate for gfx9-family: vmcnt(0), expcnt and lgkmcnt left at max
 constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kStripeBase = 64;
@@ -129,32 +132,27 @@ void convert_values(const double *src, size_t n, int32_t dtype, std::vector<uint
 // kernels
 // ----------------------------------------------------------------------------
 
-// Rows of chunks [c0, c1): the chunk kernel for k <= 2, lane groups for k >= 4.
-template <typename VT, int K, int G, bool REC, bool COH>
+// Rows of chunks [c0, c1), one chunk after another.
+template <typename VT, int K, bool REC, bool COH>
 __device__ __forceinline__ void chunks_body(int c0, int c1, const int32_t *__restrict__ chunk_row,
                                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                             const VT *__restrict__ val, const double *__restrict__ x,
                                             double *__restrict__ y, int q, const double *__restrict__ yq2,
                                             const RecArgs &rec) {
-    if constexpr (K <= 2) {
-        __shared__ ChunkLds<VT, K> lds;
-        for (int c = c0; c < c1; ++c)
-            chunk_pass<VT, K, REC, COH>(chunk_row[c], chunk_row[c + 1], rowptr, col, val, x, y, q, yq2, rec, lds);
-    } else {
-        rows_pass<VT, K, G, REC, COH>(chunk_row[c0], chunk_row[c1], rowptr, col, val, x, y, q, yq2, rec);
-    }
+    __shared__ ChunkLds<VT, K> lds;
+    for (int c = c0; c < c1; ++c)
+        chunk_pass<VT, K, REC, COH>(chunk_row[c], chunk_row[c + 1], rowptr, col, val, x, y, q, yq2, rec, lds);
 }
 
 // Baseline SpMV: one workgroup per chunk.
-template <typename VT, int K, int G, bool REC>
+template <typename VT, int K, bool REC>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(const int32_t *__restrict__ chunk_row,
                                                       const int32_t *__restrict__ rowptr,
                                                       const int32_t *__restrict__ col,
                                                       const VT *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y, int q,
                                                       const double *__restrict__ yq2, RecArgs rec) {
-    chunks_body<VT, K, G, REC, false>(blockIdx.x, blockIdx.x + 1, chunk_row, rowptr, col, val, x, y, q, yq2,
-                                      rec);
+    chunks_body<VT, K, REC, false>(blockIdx.x, blockIdx.x + 1, chunk_row, rowptr, col, val, x, y, q, yq2, rec);
 }
 
 struct MpkArgs {
@@ -172,7 +170,8 @@ struct MpkArgs {
     uint32_t *flags;
     uint32_t *ctrl;
     uint32_t epoch;
-    int32_t nstripes;
+    int32_t nstreams;
+    int32_t stream_ptr[kMaxStreams + 1];
     int64_t watchdog;
 };
 
@@ -219,41 +218,50 @@ __device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
     return a.ctrl + kStripeBase + s * kStripeStride;
 }
 
-template <typename VT, int K, int G, bool REC>
+template <typename VT, int K, bool REC>
 __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec) {
-    // Tickets are dealt over `nstripes` counters: stripe s holds tickets
-    // s, s + S, s + 2S, ...  A workgroup joins stripe (arrival index mod S) and
-    // takes that stripe's tickets in increasing order, one at a time.  Every
-    // ticket only waits for earlier tickets and any S running workgroups
-    // cover all stripes, so the smallest unfinished ticket is always held by,
-    // or next for, a running workgroup whose earlier tickets are done: the
-    // grid needs no co-residency.  The last workgroup to leave resets the
-    // counters.
-    __shared__ int s_stripe, s_ok;
+    // The tickets form `nstreams` streams (1, or 8 XCD slices); workgroup b
+    // serves stream b % nstreams.  Inside a stream the tickets are dealt over
+    // S counters: sub-stripe s holds the stream's tickets s, s + S, ...;
+    // a workgroup joins sub-stripe (its arrival index in the stream mod S)
+    // and takes that sub-stripe's tickets in increasing order, one at a time.
+    // Every ticket only waits for earlier tickets of the global order, every
+    // stream has at least S workgroups and any S of them cover its
+    // sub-stripes, so the smallest unfinished ticket is always held by, or
+    // next for, a running workgroup whose earlier tickets are done: the grid
+    // needs no co-residency.  The last workgroup to leave resets the counters.
+    __shared__ int s_sub, s_ok;
     __shared__ int s_next[2];
-    const int S = a.nstripes;
+    const int nS = a.nstreams;
+    const int stream = blockIdx.x % nS;
+    const int in_stream = (gridDim.x - stream + nS - 1) / nS;
+    const int S = min(kMaxStripes / nS, in_stream);
+    const int base = a.stream_ptr[stream];
+    const int len = a.stream_ptr[stream + 1] - base;
     const int64_t NK = (int64_t)a.n * K;
     const VT *val = reinterpret_cast<const VT *>(a.val);
     if (threadIdx.x == 0) {
-        const uint32_t arrival = __hip_atomic_fetch_add(a.ctrl + 0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int st = (int)(arrival % (uint32_t)S);
-        const uint32_t k = __hip_atomic_fetch_add(stripe_counter(a, st), 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        s_stripe = st;
-        s_next[0] = (int)min<int64_t>((int64_t)st + (int64_t)k * S, a.ntickets);
+        const uint32_t arrival =
+            __hip_atomic_fetch_add(a.ctrl + kArrivalBase + stream, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int sub = (int)(arrival % (uint32_t)S);
+        const uint32_t k = __hip_atomic_fetch_add(stripe_counter(a, stream * (kMaxStripes / nS) + sub), 1u,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_sub = sub;
+        s_next[0] = (int)min<int64_t>((int64_t)sub + (int64_t)k * S, len);
     }
     __syncthreads();
-    const int stripe = s_stripe;
+    const int counter = stream * (kMaxStripes / nS) + s_sub;
+    const int sub = s_sub;
     int t = s_next[0];
-    for (int it = 1; t < a.ntickets; ++it) {
-        const int w = a.work[t];
+    for (int it = 1; t < len; ++it) {
+        const int w = a.work[base + t];
         const int tile = w >> 6;
         const int q = (w & 63) + 1;
         if (q > 1) {
             if (threadIdx.x == 0) s_ok = 1;
             __syncthreads();
             if (threadIdx.x < 64) {
-                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep3 + 6 * tile, a, t);
+                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep3 + 6 * tile, a, base + t);
                 if (!ok && threadIdx.x == 0) s_ok = 0;
             }
             __syncthreads();
@@ -262,18 +270,18 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
-        chunks_body<VT, K, G, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk_row, a.rowptr,
-                                         a.col, val, xin, yout, q, yq2, rec);
+        chunks_body<VT, K, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk_row, a.rowptr, a.col,
+                                      val, xin, yout, q, yq2, rec);
         // The next ticket is taken only now: a workgroup never holds a ticket
         // it is not working on, so no ticket waits behind an idle one.
         uint32_t kn = 0;
         if (threadIdx.x == 0)
-            kn = __hip_atomic_fetch_add(stripe_counter(a, stripe), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            kn = __hip_atomic_fetch_add(stripe_counter(a, counter), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // Release: the tile's results were written with agent-scope stores;
         // every wavefront waits until its stores have completed (vmcnt = 0)
         // before the workgroup barrier, after which the flag is published.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        if (threadIdx.x == 0) s_next[it & 1] = (int)min<int64_t>((int64_t)stripe + (int64_t)kn * S, a.ntickets);
+        if (threadIdx.x == 0) s_next[it & 1] = (int)min<int64_t>((int64_t)sub + (int64_t)kn * S, len);
         __syncthreads();
         if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, a.epoch);
         t = s_next[it & 1];
@@ -281,8 +289,8 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     if (threadIdx.x == 0) {
         const uint32_t done = __hip_atomic_fetch_add(a.ctrl + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (done == gridDim.x - 1) {
-            for (int st = 0; st < S; ++st) st_agent(stripe_counter(a, st), 0u);
-            st_agent(a.ctrl + 0, 0u);
+            for (int st = 0; st < kMaxStripes; ++st) st_agent(stripe_counter(a, st), 0u);
+            for (int st = 0; st < kMaxStreams; ++st) st_agent(a.ctrl + kArrivalBase + st, 0u);
             st_agent(a.ctrl + 1, 0u);
         }
     }
@@ -323,70 +331,27 @@ __global__ __launch_bounds__(kBlock) void bw_probe(const double2 *__restrict__ b
 }
 
 // ----------------------------------------------------------------------------
-// launch dispatch: value type x columns K x lanes G x recurrence
+// launch dispatch: value type x right-hand sides K x recurrence
 // ----------------------------------------------------------------------------
 
 template <typename VT, int K, bool REC>
 struct Dispatch {
-    static hipError_t spmv(int G, int blocks, hipStream_t s, const int32_t *chunks, const int32_t *rp,
-                           const int32_t *ci, const void *v, const double *x, double *y, int q,
-                           const double *yq2, const RecArgs &rec) {
-        if constexpr (K <= 2) G = 32;  // the chunk kernel does not use lane groups
-        const VT *val = reinterpret_cast<const VT *>(v);
-#define MPK_SPMV_CASE(GG)                                                                              \
-    case GG:                                                                                           \
-        if constexpr (GG >= K && (K > 2 || GG == 32)) {                                                \
-            hipLaunchKernelGGL((spmv_kernel<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, chunks, \
-                               rp, ci, val, x, y, q, yq2, rec);                                        \
-            return hipGetLastError();                                                                  \
-        }                                                                                              \
-        break;
-        switch (G) {
-            MPK_SPMV_CASE(4)
-            MPK_SPMV_CASE(8)
-            MPK_SPMV_CASE(16)
-            MPK_SPMV_CASE(32)
-            MPK_SPMV_CASE(64)
-        }
-#undef MPK_SPMV_CASE
-        return hipErrorInvalidValue;
+    static hipError_t spmv(int blocks, hipStream_t s, const int32_t *chunks, const int32_t *rp, const int32_t *ci,
+                           const void *v, const double *x, double *y, int q, const double *yq2,
+                           const RecArgs &rec) {
+        hipLaunchKernelGGL((spmv_kernel<VT, K, REC>), dim3(blocks), dim3(kBlock), 0, s, chunks, rp, ci,
+                           reinterpret_cast<const VT *>(v), x, y, q, yq2, rec);
+        return hipGetLastError();
     }
-    static hipError_t mpk(int G, int blocks, hipStream_t s, const MpkArgs &a, const RecArgs &rec) {
-        if constexpr (K <= 2) G = 32;
-#define MPK_RUN_CASE(GG)                                                                              \
-    case GG:                                                                                          \
-        if constexpr (GG >= K && (K > 2 || GG == 32)) {                                               \
-            MpkArgs a_ = a;                                                                           \
-            a_.nstripes = std::max(1, std::min(blocks, kMaxStripes));                                 \
-            hipLaunchKernelGGL((mpk_persistent<VT, K, GG, REC>), dim3(blocks), dim3(kBlock), 0, s, a_, rec); \
-            return hipGetLastError();                                                                 \
-        }                                                                                             \
-        break;
-        switch (G) {
-            MPK_RUN_CASE(4)
-            MPK_RUN_CASE(8)
-            MPK_RUN_CASE(16)
-            MPK_RUN_CASE(32)
-            MPK_RUN_CASE(64)
-        }
-#undef MPK_RUN_CASE
-        return hipErrorInvalidValue;
+    static hipError_t mpk(int blocks, hipStream_t s, const MpkArgs &a, const RecArgs &rec) {
+        hipLaunchKernelGGL((mpk_persistent<VT, K, REC>), dim3(blocks), dim3(kBlock), 0, s, a, rec);
+        return hipGetLastError();
     }
-    static const void *mpk_symbol(int G) {
-        if constexpr (K <= 2) G = 32;
-        switch (G) {
-            case 4: if constexpr (4 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 4, REC>; break;
-            case 8: if constexpr (8 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 8, REC>; break;
-            case 16: if constexpr (16 >= K && K > 2) return (const void *)mpk_persistent<VT, K, 16, REC>; break;
-            case 32: return (const void *)mpk_persistent<VT, K, 32, REC>;
-            case 64: if constexpr (K > 2) return (const void *)mpk_persistent<VT, K, 64, REC>; break;
-        }
-        return nullptr;
-    }
+    static const void *mpk_symbol() { return (const void *)mpk_persistent<VT, K, REC>; }
 };
 
-// What is compiled: FP64 for every K in {1,2,4,8,16,32} (recurrence for K <= 2);
-// FP32 and BF16 values for K in {1, 2} with and without the recurrence.
+// What is compiled: FP64 for every k in {1,2,4,8,16,32} (recurrence for k <= 2);
+// FP32 and BF16 values for k in {1, 2} with and without the recurrence.
 template <typename VT, bool REC>
 struct ByK {
     template <typename F>
@@ -465,6 +430,7 @@ void mpk_options_default(mpk_options *opt) {
     opt->nrhs = 1;
     opt->watchdog_spins = 0;
     opt->skew = 1;
+    opt->xcd_streams = 1;
 }
 
 const char *mpk_version(void) { return "mpk-gfx950 0.1"; }
@@ -555,7 +521,7 @@ mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info) {
     info->violating_groups = h.violating_groups;
     info->device_bytes = plan->device_bytes;
     info->workgroups = plan->workgroups;
-    info->lanes_per_row = h.lanes_per_row;
+    info->n_chunks = (int32_t)std::max<size_t>(1, h.chunk_row.size()) - 1;
     info->tile_nnz = h.tile_nnz;
     info->val_dtype = h.opt.val_dtype;
     info->plan_seconds = h.plan_seconds;
@@ -641,7 +607,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_val, vbuf.data(), h.nnz * value_bytes(h.opt.val_dtype)},
         {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
         {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
-        {plan->d_work, h.work.data(), sizeof(int32_t) * W},
+        {plan->d_work, h.work_streams.data(), sizeof(int32_t) * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
         {plan->d_chunk_row, h.chunk_row.data(), sizeof(int32_t) * h.chunk_row.size()},
         {plan->d_tile_chunk, h.tile_chunk.data(), sizeof(int32_t) * h.tile_chunk.size()},
@@ -658,13 +624,15 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     int occ = 0;
     const void *sym = nullptr;
     (void)dispatch_all(h.opt.val_dtype, h.opt.nrhs, false, [&](auto d) {
-        sym = decltype(d)::mpk_symbol(h.lanes_per_row);
+        sym = decltype(d)::mpk_symbol();
         return hipSuccess;
     });
     if (sym && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sym, kBlock, 0) != hipSuccess) occ = 0;
     if (occ <= 0) occ = 2;
     int64_t wg = h.opt.workgroups > 0 ? h.opt.workgroups : (int64_t)occ * plan->num_cus;
     wg = std::max<int64_t>(1, std::min<int64_t>(wg, std::max<int64_t>(W, 1)));
+    // every ticket stream needs workgroups of its own
+    wg = std::max<int64_t>(wg, (int64_t)h.stream_ptr.size() - 1);
     plan->workgroups = (int32_t)wg;
     plan->device_bytes = bytes;
     plan->uploaded = true;
@@ -723,6 +691,8 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.n = (int32_t)h.n;
     a.ntiles = (int32_t)h.dep_lo.size();
     a.ntickets = (int32_t)h.work.size();
+    a.nstreams = (int32_t)h.stream_ptr.size() - 1;
+    for (int i = 0; i <= kMaxStreams; ++i) a.stream_ptr[i] = h.stream_ptr[std::min<int>(i, a.nstreams)];
     a.X = X;
     a.Y = Y;
     a.flags = plan->d_flags;
@@ -731,7 +701,7 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.watchdog = h.opt.watchdog_spins > 0 ? h.opt.watchdog_spins : (int64_t)1 << 24;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.nrhs, rec != nullptr, [&](auto d) {
-        return decltype(d)::mpk(h.lanes_per_row, plan->workgroups, s, a, ra);
+        return decltype(d)::mpk(plan->workgroups, s, a, ra);
     });
     if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("mpk launch: ") + hipGetErrorString(e));
     return MPK_OK;
@@ -747,7 +717,7 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
     if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
-    const int K = h.opt.nrhs, G = h.lanes_per_row;
+    const int K = h.opt.nrhs;
     const int blocks = (int)(h.chunk_row.size() - 1);
     const int64_t NK = h.n * K;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -756,8 +726,8 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
         hipError_t e = dispatch_all(h.opt.val_dtype, K, rec != nullptr, [&](auto d) {
-            return decltype(d)::spmv(G, blocks, s, plan->d_chunk_row, plan->d_rowptr, plan->d_col, plan->d_val,
-                                     x, y, q, yq2, ra);
+            return decltype(d)::spmv(blocks, s, plan->d_chunk_row, plan->d_rowptr, plan->d_col, plan->d_val, x, y,
+                                     q, yq2, ra);
         });
         if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
     }
@@ -794,19 +764,12 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     if (st != MPK_OK) return st;
     if (o.nrhs < 1 || o.nrhs > MPK_MAX_NRHS || !supported(o.val_dtype, o.nrhs, false))
         return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
-    if (o.lanes_per_row != 0) {
-        int g = o.lanes_per_row;
-        if (g < 4 || g > 64 || (g & (g - 1)) || g < o.nrhs)
-            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
-    }
     mpk_spmv *h = new (std::nothrow) mpk_spmv();
     if (!h) return fail(MPK_ERR_OOM, "host allocation failed");
     h->n = A->n;
     h->nnz = A->nnz;
     h->dtype = o.val_dtype;
     h->nrhs = o.nrhs;
-    double mean_row = A->n > 0 ? (double)A->nnz / (double)A->n : 1.0;
-    h->lanes = o.lanes_per_row ? o.lanes_per_row : auto_lanes(mean_row, o.nrhs);
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
     std::vector<int32_t> chunks;
@@ -846,8 +809,8 @@ static mpk_status spmv_launch(mpk_spmv *h, const double *x, double *y, hipStream
     RecArgs ra;
     (void)fill_rec(nullptr, 1, h->nrhs, ra);
     hipError_t e = dispatch_all(h->dtype, h->nrhs, false, [&](auto d) {
-        return decltype(d)::spmv(h->lanes, (int)h->nchunks, s, h->d_chunk_row, h->d_rowptr, h->d_col, h->d_val, x,
-                                 y, 1, nullptr, ra);
+        return decltype(d)::spmv((int)h->nchunks, s, h->d_chunk_row, h->d_rowptr, h->d_col, h->d_val, x, y, 1,
+                                 nullptr, ra);
     });
     if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
     return MPK_OK;

@@ -41,11 +41,12 @@ struct HostPlan {
     std::vector<int32_t> dep3;       // 6*n_tiles: (lo, hi) in groups g-1, g, g+1 (lo > hi: none)
     std::vector<int32_t> group_tile; // G+1
     std::vector<int32_t> work;       // tickets: tile*64 + (q-1)
+    std::vector<int32_t> stream_ptr; // xcd_streams+1: ticket streams, each in `work` order
+    std::vector<int32_t> work_streams;  // the tickets regrouped by stream
     std::vector<int32_t> chunk_row;  // n_chunks+1: kernel work units inside tiles
     std::vector<int32_t> tile_chunk; // n_tiles+1
 
     int64_t max_level_rows = 0, max_group_nnz = 0, violating_groups = 0;
-    int32_t lanes_per_row = 0;
     int32_t tile_nnz = 0;
     double plan_seconds = 0.0;
 };
@@ -72,9 +73,6 @@ void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_
 
 // Nonzeros per kernel chunk for k right-hand sides (matches the device code).
 int32_t chunk_nnz_host(int32_t k);
-
-// Default lanes-per-row choice for a mean row length and k columns.
-int32_t auto_lanes(double mean_row, int32_t k);
 
 // Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
 int32_t bytes_per_nnz(int32_t dtype);

@@ -36,16 +36,7 @@ int32_t bytes_per_nnz(int32_t dtype) {
     }
 }
 
-int32_t auto_lanes(double mean_row, int32_t k) {
-    // enough lanes that one pass covers most of a row, at least k
-    int32_t g = 4;
-    double per_slot = mean_row;
-    while (g < 64 && (double)(g / std::max<int32_t>(1, k)) < per_slot * 0.75) g <<= 1;
-    while (g < k) g <<= 1;
-    return std::min<int32_t>(std::max<int32_t>(g, 4), 64);
-}
-
-int32_t chunk_nnz_host(int32_t k) { return k == 1 ? 2048 : k == 2 ? 1024 : 4096 / k; }
+int32_t chunk_nnz_host(int32_t k) { return 2048 / k; }
 
 template <typename RP>
 static void append_chunks_t(const RP *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
@@ -252,13 +243,10 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
     if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
     if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
     if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
-    if (opt.lanes_per_row != 0) {
-        int32_t g = opt.lanes_per_row;
-        if (g < 4 || g > 64 || (g & (g - 1)) || g < opt.nrhs)
-            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
-    }
+    if (opt.reserved0 != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+    if (opt.xcd_streams != 1 && opt.xcd_streams != 8) return fail(MPK_ERR_ARG, "xcd_streams must be 1 or 8");
     const int64_t n = hp.n;
     const int64_t L = (int64_t)hp.level_ptr.size() - 1;
     const int64_t nnz_total = hp.nnz;
@@ -316,8 +304,6 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         if (tile_nnz <= 0) tile_nnz = 32768;
         const int64_t max_tile_rows = 1 << 14;
         hp.tile_nnz = (int32_t)tile_nnz;
-        double mean_row = n > 0 ? (double)nnz_total / (double)n : 1.0;
-        hp.lanes_per_row = opt.lanes_per_row ? opt.lanes_per_row : auto_lanes(mean_row, opt.nrhs);
         hp.tile_row.clear();
         hp.tile_group.clear();
         hp.group_tile.clear();
@@ -433,6 +419,28 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
             const int32_t q = (int32_t)(nd.first % (p + 1)), gi = (int32_t)nd.second;
             for (int32_t t = hp.group_tile[gi]; t < hp.group_tile[gi + 1]; ++t) hp.work.push_back(t * 64 + (q - 1));
         }
+
+        // Ticket streams.  With 8 streams the tiles of each level group are
+        // cut into 8 consecutive slices (slice s = tiles whose position in the
+        // group falls in [s/8, (s+1)/8)); stream s holds the tickets of slice
+        // s in the order above.  A tile of a level reads the neighbour levels
+        // at about the same relative position, so its dependencies mostly
+        // stay in its own stream.
+        const int S = opt.xcd_streams;
+        std::vector<int32_t> tile_stream(T, 0);
+        if (S > 1)
+            for (int64_t gi = 0; gi < G; ++gi) {
+                const int64_t t0 = hp.group_tile[gi], nt = hp.group_tile[gi + 1] - t0;
+                for (int64_t t = t0; t < t0 + nt; ++t) tile_stream[t] = (int32_t)(((t - t0) * S) / nt);
+            }
+        hp.stream_ptr.assign(S + 1, 0);
+        for (int32_t w : hp.work) hp.stream_ptr[tile_stream[w >> 6] + 1]++;
+        for (int sidx = 0; sidx < S; ++sidx) hp.stream_ptr[sidx + 1] += hp.stream_ptr[sidx];
+        hp.work_streams.assign(hp.work.size(), 0);
+        {
+            std::vector<int32_t> fill(hp.stream_ptr.begin(), hp.stream_ptr.end() - 1);
+            for (int32_t w : hp.work) hp.work_streams[fill[tile_stream[w >> 6]]++] = w;
+        }
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");
     }
@@ -450,11 +458,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
     if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
     if (opt.root_mode < 0 || opt.root_mode > 1) return fail(MPK_ERR_ARG, "bad root_mode");
-    if (opt.lanes_per_row != 0) {
-        int32_t g = opt.lanes_per_row;
-        if (g < 4 || g > 64 || (g & (g - 1)) || g < opt.nrhs)
-            return fail(MPK_ERR_ARG, "lanes_per_row must be a power of two in [max(4,k), 64]");
-    }
+    if (opt.reserved0 != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
 

@@ -81,13 +81,14 @@ def test_c1_2d5pt(tile_nnz, C):
 
 @pytest.mark.parametrize("root_mode", [0, 1])
 @pytest.mark.parametrize("p", [1, 4, 8])
-@pytest.mark.parametrize("lanes", [0, 4, 64])
-def test_27pt_random(root_mode, p, lanes):
+@pytest.mark.parametrize("tile", [300, 2000, 9000])
+@pytest.mark.parametrize("streams,skew", [(1, 1), (8, 2)])
+def test_27pt_random(root_mode, p, tile, streams, skew):
     A, _ = W.stencil_27pt_random(24, seed=p + root_mode)
     x = W.uniform_vector(A.n, seed=p)
     ref = O.spmv_powers(A, x, p)
-    Y, pl = run_mpk(A, x, p, 2 << 20, root_mode=root_mode, tile_nnz=2000, lanes_per_row=lanes)
-    assert pl.info()["n_tiles"] > 50
+    Y, pl = run_mpk(A, x, p, 2 << 20, root_mode=root_mode, tile_nnz=tile, xcd_streams=streams, skew=skew)
+    assert pl.info()["n_tiles"] > 10
     check_powers(Y, ref)
 
 
@@ -163,6 +164,8 @@ def test_multi_rhs(k):
     X = W.gaussian_block(A.n, k, seed=k)
     ref = O.spmv_powers(A, X, 6)
     Y, _ = run_mpk(A, X, 6, 1 << 19, nrhs=k, root_mode=1, tile_nnz=2500)
+    check_powers(Y, ref)
+    Y, _ = run_mpk(A, X, 6, 1 << 19, nrhs=k, root_mode=1, tile_nnz=700, xcd_streams=8, workgroups=24)
     check_powers(Y, ref)
 
 
@@ -273,3 +276,72 @@ def test_run_argument_errors():
     pl.upload()
     with pytest.raises(MpkError, match="MPK_ERR_ARG"):
         pl.run(Y[0], Y)  # X inside Y
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 32])
+def test_long_rows_and_chunk_edges(k):
+    # rows longer than a chunk (one dense row and power-law rows) take the
+    # strided path; chunk boundaries fall at every position
+    rng = np.random.default_rng(k)
+    A = W.zipf_rows(4000, 1.5, seed=k)
+    dense = np.arange(4000, dtype=np.int32)
+    rowptr = np.concatenate([[0], A.rowptr[1:] - A.rowptr[1] + 4000]).astype(np.int64)
+    col = np.concatenate([dense, A.col[A.rowptr[1]:]]).astype(np.int32)
+    val = np.concatenate([rng.uniform(-1, 1, 4000) / 4000, A.val[A.rowptr[1]:]])
+    B = W.CSR(4000, rowptr, col, val)
+    X = W.gaussian_block(B.n, k, seed=k) if k > 1 else W.uniform_vector(B.n, seed=k)
+    ref = O.spmv_powers(B, X, 4)
+    for tile in (500, 5000):
+        Y, _ = run_mpk(B, X, 4, 1 << 18, nrhs=k, tile_nnz=tile, root_mode=1)
+        check_powers(Y, ref)
+    Yb, _ = run_mpk(B, X, 4, 1 << 18, nrhs=k, baseline=True)
+    check_powers(Yb, ref)
+
+
+def test_retune_then_run():
+    dev = _dev()
+    A, _ = W.stencil_27pt_random(18, seed=12)
+    x = W.uniform_vector(A.n, seed=12)
+    pl = Plan(A, 4, 1 << 20, root_mode=1)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    for p, C, kw in [(8, 1 << 19, {"skew": 2, "tile_nnz": 1200}), (3, 1 << 22, {"val_dtype": "f32"}),
+                     (6, 1 << 20, {"workgroups": 40})]:
+        pl.retune(p, C, root_mode=1, **kw)
+        Y = torch.full((p, A.n), float("nan"), dtype=torch.float64, device=dev)
+        pl.run(X, Y)
+        pl.status()
+        out = _unpermute_powers(Y.cpu().numpy(), perm)
+        if kw.get("val_dtype") == "f32":
+            ref = O.spmv_powers_lowp(A, x, p, "f32")
+            assert max(_rel_err(out[q], ref[q]) for q in range(p)) < 1e-5
+        else:
+            check_powers(out, O.spmv_powers(A, x, p))
+
+
+@pytest.mark.parametrize("baseline", [False, True])
+def test_chebyshev_propagator(baseline):
+    from paper_2205_01598_amd.cheb import ChebPropagator
+
+    dev = _dev()
+    A = W.anderson_3d(12, seed=3)
+    x = W.random_phase_state(A.n, seed=3)
+    M, p, r_dt = 32, 8, 10.0
+    c = O.cheb_coefficients(M, r_dt)
+    ref1 = O.cheb_propagate(A, x, c)
+    ref2 = O.cheb_propagate(A, ref1, c)
+    pl = Plan(A, p, 1 << 20, nrhs=2, root_mode=1, tile_nnz=700, skew=2)
+    perm = pl.arrays()[0].astype(np.int64)
+    prop = ChebPropagator(pl, M, r_dt)
+    assert np.allclose(prop.c, c, rtol=0, atol=1e-15)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    a1 = torch.empty_like(X)
+    a2 = torch.empty_like(X)
+    prop.step(X, a1, baseline=baseline)
+    prop.step(a1, a2, baseline=baseline)
+    pl.status()
+    for a, ref in ((a1, ref1), (a2, ref2)):
+        h = np.empty((A.n, 2))
+        h[perm] = a.cpu().numpy()
+        assert _rel_err(h, ref) <= 1e-12
+    assert abs(np.linalg.norm(h) - 1.0) < 1e-10
