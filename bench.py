@@ -195,6 +195,35 @@ def probe():
         print(f"{mb:8d}  {mb * (1 << 20) / t1 / 1e6:12.1f}  {16 * mb * (1 << 20) / t2 / 1e6:12.1f}", flush=True)
 
 
+def bench_learned_tuner(torch, plan, X, Y, p, log):
+    """Train the cost model on the committed sweep database (held-out split),
+    report its choices against the sweep's best and the untuned default, and
+    apply it to the headline matrix."""
+    from paper_2205_01598_amd import tune
+
+    db = os.path.join(ROOT, "paper_2205_01598_amd", "data", "tuner_sweep_mi355x.jsonl")
+    if not os.path.exists(db):
+        return None
+    recs = tune.load_db(db)
+    train, test = tune.split_seeds(recs)
+    t0 = time.time()
+    tuner = tune.LearnedTuner(hidden=64, seed=0)
+    loss = tuner.fit(train, steps=3000)
+    out = {"train_matrices": len({r["seed"] for r in train}), "held_out_matrices": len({r["seed"] for r in test}),
+           "train_seconds": round(time.time() - t0, 2), "final_train_loss": round(loss, 5),
+           "held_out": tune.evaluate(tuner, test)}
+    tune._apply(plan, p, tune.DEFAULT)
+    feats = tune.plan_features(plan)
+    t_def = tune.time_run(torch, plan, X, Y, reps=10)
+    cfg = tuner.choose(feats)
+    tune._apply(plan, p, cfg)
+    t_pick = tune.time_run(torch, plan, X, Y, reps=10)
+    out["headline_matrix"] = {"chosen": cfg, "mpk_ms": round(t_pick, 4), "default_mpk_ms": round(t_def, 4),
+                              "gain_over_default": round(t_def / t_pick, 3)}
+    log(f"learned tuner: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +370,7 @@ def main():
 
     extra = {}
     if not args.no_extra:
+        extra["learned_tuner"] = bench_learned_tuner(torch, plan, X, Y, p, log)
         del plan
         extra["small_2d"] = bench_small_2d(torch, Plan, W, dev)
         log(f"small 2D: {extra['small_2d']}")

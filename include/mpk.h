@@ -43,6 +43,7 @@ extern "C" {
 
 #define MPK_MAX_POWER 32
 #define MPK_MAX_NRHS 32
+#define MPK_NUM_FEATURES 24
 
 typedef int32_t mpk_status;
 enum {
@@ -78,7 +79,7 @@ typedef struct mpk_options {
     int32_t val_dtype;        /* mpk_dtype of stored matrix values (default MPK_F64) */
     int32_t nrhs;             /* k, right-hand sides per run, 1..MPK_MAX_NRHS (default 1) */
     int32_t workgroups;       /* persistent-kernel grid size; 0 = automatic */
-    int32_t tile_nnz;         /* target nonzeros per device tile; 0 = automatic */
+    int32_t tile_nnz;         /* target nonzeros per device tile; 0 = 8192 */
     int32_t reserved0;        /* must be 0 */
     int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
@@ -112,6 +113,8 @@ typedef struct mpk_plan_info {
     int32_t tile_nnz;
     int32_t val_dtype;
     double plan_seconds;      /* host time spent in mpk_plan_create */
+    double phase_seconds[4];  /* of which: graph of A + A^T, root search + BFS, renumbering,
+                                 groups/schedule/tiles */
 } mpk_plan_info;
 
 /* Three-term recurrence epilogue for mpk_run / mpk_run_baseline (Sec. 7,
@@ -196,6 +199,13 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
  * limiting the reads of a group to its two neighbour groups). */
 mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges);
 
+/* Matrix and level features for the learned tuner, host, MPK_NUM_FEATURES
+ * doubles: log10 N, log10 nnz, mean / standard deviation / log2(max+1) of the
+ * row lengths, log10 of the number of levels, widest level / N, log2 p, then a
+ * 16-bin histogram of the level widths (fraction of levels with width/N in
+ * [2^-(b+1), 2^-b), b = 0..15, the last bin open below). */
+mpk_status mpk_plan_features(const mpk_plan *plan, double *features);
+
 /* Allocate the plan's device buffers on the current HIP device and copy the
  * renumbered matrix (converted to val_dtype, round to nearest even) and the
  * tile tables there.  Synchronous.  Errors: MPK_ERR_OOM, MPK_ERR_HIP. */
@@ -243,6 +253,28 @@ void spmv_destroy(mpk_spmv *h);
  * *sink (device, one double).  Time it with events on `stream`. */
 mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups,
                         double *sink, void *stream);
+
+/* ---- learned tuner: a 3-layer perceptron, FP32, on the device -------------
+ * out = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with D inputs and H hidden
+ * units (H <= 256).  Parameters are one float array laid out W1[H][D], b1[H],
+ * W2[H][H], b2[H], w3[H], b3 (mpk_mlp_param_count(D, H) floats).  All arrays
+ * are device memory; calls are asynchronous on `stream`. */
+int64_t mpk_mlp_param_count(int32_t D, int32_t H);
+/* Forward pass for B samples X[B][D]: out[B]; cache[B][2H] keeps the
+ * pre-activations for the backward pass. */
+mpk_status mpk_mlp_forward(const float *params, int32_t D, int32_t H, const float *X, int32_t B, float *out,
+                           float *cache, void *stream);
+/* Gradient of the mean squared error (1/B) sum (out - y)^2 with respect to
+ * every parameter, into grads[param_count]; work needs B*(2H+1) floats;
+ * loss (one float, may be NULL) receives the loss.  Sums over the batch run
+ * in sample order, so results are deterministic. */
+mpk_status mpk_mlp_backward(const float *params, int32_t D, int32_t H, const float *X, const float *y, int32_t B,
+                            const float *out, const float *cache, float *work, float *grads, float *loss,
+                            void *stream);
+/* One Adam step (step = 1, 2, ...): m, v are the moment buffers (zero before
+ * step 1), bias-corrected update params -= lr mhat / (sqrt(vhat) + eps). */
+mpk_status mpk_mlp_adam(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void *stream);
 
 const char *mpk_status_string(mpk_status s);
 const char *mpk_last_error(void);

@@ -13,6 +13,7 @@ LIBPATH = os.path.join(HERE, "libmpk.so")
 
 MPK_MAX_POWER = 32
 MPK_MAX_NRHS = 32
+MPK_NUM_FEATURES = 24
 
 STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_OOM", -4: "MPK_ERR_HIP",
           -5: "MPK_ERR_TIMEOUT", -6: "MPK_ERR_UNSUPPORTED", -7: "MPK_ERR_STATE"}
@@ -50,7 +51,7 @@ class mpk_plan_info(ctypes.Structure):
                 ("violating_groups", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
                 ("workgroups", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("tile_nnz", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("phase_seconds", ctypes.c_double * 4)]
 
 
 class mpk_recurrence(ctypes.Structure):
@@ -76,6 +77,7 @@ SIGNATURES = {
     "mpk_plan_matrix": (ctypes.c_int32, [_P, _I64P, _I32P, _F64P]),
     "mpk_plan_tiles": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
     "mpk_plan_tile_deps": (ctypes.c_int32, [_P, _I32P]),
+    "mpk_plan_features": (ctypes.c_int32, [_P, _F64P]),
     "mpk_plan_upload": (ctypes.c_int32, [_P]),
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "mpk_run": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
@@ -88,6 +90,12 @@ SIGNATURES = {
     "spmv_powers_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
     "spmv_destroy": (None, [_P]),
     "mpk_bw_probe": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "mpk_mlp_param_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32]),
+    "mpk_mlp_forward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]),
+    "mpk_mlp_backward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P,
+                                          _P, _P, _P]),
+    "mpk_mlp_adam": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
     "mpk_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "mpk_last_error": (ctypes.c_char_p, []),
     "mpk_version": (ctypes.c_char_p, []),

@@ -491,10 +491,11 @@ mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, cons
         plan->uploaded = false;
         plan->device_bytes = 0;
     }
-    HostPlan backup = plan->hp;
+    ScheduleState backup;
+    save_schedule(plan->hp, backup);
     mpk_status st = build_schedule(plan->hp, p, cache_bytes, o);
     if (st != MPK_OK) {
-        plan->hp = std::move(backup);
+        restore_schedule(plan->hp, backup);
         if (was_uploaded) (void)mpk_plan_upload(plan);
         return st;
     }
@@ -525,6 +526,7 @@ mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info) {
     info->tile_nnz = h.tile_nnz;
     info->val_dtype = h.opt.val_dtype;
     info->plan_seconds = h.plan_seconds;
+    for (int i = 0; i < 4; ++i) info->phase_seconds[i] = h.phase_seconds[i];
     return MPK_OK;
 }
 
@@ -563,6 +565,12 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
 mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges) {
     if (!plan) return fail(MPK_ERR_ARG, "null plan");
     if (ranges) std::copy(plan->hp.dep3.begin(), plan->hp.dep3.end(), ranges);
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_features(const mpk_plan *plan, double *features) {
+    if (!plan || !features) return fail(MPK_ERR_ARG, "null argument");
+    plan_features(plan->hp, features);
     return MPK_OK;
 }
 

@@ -49,7 +49,21 @@ struct HostPlan {
     int64_t max_level_rows = 0, max_group_nnz = 0, violating_groups = 0;
     int32_t tile_nnz = 0;
     double plan_seconds = 0.0;
+    double phase_seconds[4] = {0, 0, 0, 0};
 };
+
+// The fields build_schedule rewrites (saved so a failed retune can restore them).
+struct ScheduleState {
+    int32_t p;
+    uint64_t cache_bytes;
+    mpk_options opt;
+    std::vector<int32_t> group_ptr, schedule, tile_row, tile_group, dep_lo, dep_hi, dep3, group_tile, work,
+        stream_ptr, work_streams, chunk_row, tile_chunk;
+    int64_t max_group_nnz, violating_groups;
+    int32_t tile_nnz;
+};
+void save_schedule(HostPlan &hp, ScheduleState &s);     // moves the fields out
+void restore_schedule(HostPlan &hp, ScheduleState &s);  // moves them back
 
 // Runs every host step of the plan.  Returns MPK_OK or an error (message set).
 mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
@@ -59,6 +73,9 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
 // options (level groups, schedule, tiles, dependencies, tickets); reuses the
 // levels and renumbered matrix already in hp.
 mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const mpk_options &opt);
+
+// Matrix/plan features for the learned tuner (MPK_NUM_FEATURES values).
+void plan_features(const HostPlan &hp, double *f);
 
 // Validation shared by plan and SpMV creation.
 mpk_status validate_csr(const mpk_csr *A);

@@ -249,7 +249,6 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
     if (opt.xcd_streams != 1 && opt.xcd_streams != 8) return fail(MPK_ERR_ARG, "xcd_streams must be 1 or 8");
     const int64_t n = hp.n;
     const int64_t L = (int64_t)hp.level_ptr.size() - 1;
-    const int64_t nnz_total = hp.nnz;
     hp.p = p;
     hp.cache_bytes = cache_bytes;
     const int32_t root_mode = hp.opt.root_mode;
@@ -301,7 +300,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
 
         // ---- device tiles --------------------------------------------------------------
         int64_t tile_nnz = opt.tile_nnz;
-        if (tile_nnz <= 0) tile_nnz = 32768;
+        if (tile_nnz <= 0) tile_nnz = 8192;
         const int64_t max_tile_rows = 1 << 14;
         hp.tile_nnz = (int32_t)tile_nnz;
         hp.tile_row.clear();
@@ -447,6 +446,79 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
     return MPK_OK;
 }
 
+void save_schedule(HostPlan &hp, ScheduleState &s) {
+    s.p = hp.p;
+    s.cache_bytes = hp.cache_bytes;
+    s.opt = hp.opt;
+    s.group_ptr = hp.group_ptr;
+    s.schedule = hp.schedule;
+    s.tile_row = hp.tile_row;
+    s.tile_group = hp.tile_group;
+    s.dep_lo = hp.dep_lo;
+    s.dep_hi = hp.dep_hi;
+    s.dep3 = hp.dep3;
+    s.group_tile = hp.group_tile;
+    s.work = hp.work;
+    s.stream_ptr = hp.stream_ptr;
+    s.work_streams = hp.work_streams;
+    s.chunk_row = hp.chunk_row;
+    s.tile_chunk = hp.tile_chunk;
+    s.max_group_nnz = hp.max_group_nnz;
+    s.violating_groups = hp.violating_groups;
+    s.tile_nnz = hp.tile_nnz;
+}
+
+void restore_schedule(HostPlan &hp, ScheduleState &s) {
+    hp.p = s.p;
+    hp.cache_bytes = s.cache_bytes;
+    hp.opt = s.opt;
+    hp.group_ptr.swap(s.group_ptr);
+    hp.schedule.swap(s.schedule);
+    hp.tile_row.swap(s.tile_row);
+    hp.tile_group.swap(s.tile_group);
+    hp.dep_lo.swap(s.dep_lo);
+    hp.dep_hi.swap(s.dep_hi);
+    hp.dep3.swap(s.dep3);
+    hp.group_tile.swap(s.group_tile);
+    hp.work.swap(s.work);
+    hp.stream_ptr.swap(s.stream_ptr);
+    hp.work_streams.swap(s.work_streams);
+    hp.chunk_row.swap(s.chunk_row);
+    hp.tile_chunk.swap(s.tile_chunk);
+    hp.max_group_nnz = s.max_group_nnz;
+    hp.violating_groups = s.violating_groups;
+    hp.tile_nnz = s.tile_nnz;
+}
+
+void plan_features(const HostPlan &hp, double *f) {
+    for (int i = 0; i < MPK_NUM_FEATURES; ++i) f[i] = 0.0;
+    const int64_t n = hp.n, nnz = hp.nnz, L = (int64_t)hp.level_ptr.size() - 1;
+    if (n <= 0) return;
+    double mean = (double)nnz / (double)n, var = 0.0;
+    int64_t mx = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t len = hp.rowptr[r + 1] - hp.rowptr[r];
+        var += ((double)len - mean) * ((double)len - mean);
+        mx = std::max(mx, len);
+    }
+    f[0] = std::log10((double)n);
+    f[1] = std::log10((double)std::max<int64_t>(nnz, 1));
+    f[2] = mean;
+    f[3] = std::sqrt(var / (double)n);
+    f[4] = std::log2((double)mx + 1.0);
+    f[5] = std::log10((double)std::max<int64_t>(L, 1));
+    f[6] = (double)hp.max_level_rows / (double)n;
+    f[7] = std::log2((double)hp.p);
+    // level-width histogram: fraction of levels with width/N in
+    // [2^-(b+1), 2^-b), b = 0..15 (the last bin takes everything narrower)
+    for (int64_t l = 0; l < L; ++l) {
+        const double w = (double)(hp.level_ptr[l + 1] - hp.level_ptr[l]) / (double)n;
+        int b = (int)std::floor(-std::log2(w));
+        b = std::min(std::max(b, 0), 15);
+        f[8 + b] += 1.0 / (double)L;
+    }
+}
+
 mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            const mpk_options &opt, HostPlan &hp) {
     auto t0 = std::chrono::steady_clock::now();
@@ -471,11 +543,17 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
 
     try {
         // ---- graph, root, levels -------------------------------------------------
+        auto now = [] { return std::chrono::steady_clock::now(); };
+        auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+        auto ta = now();
         Graph g;
         build_graph(A, g);
+        auto tb = now();
         hp.root = 0;
         if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
         bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+        hp.phase_seconds[0] = secs(ta, tb);
+        hp.phase_seconds[1] = secs(tb, now());
         { Graph().adj.swap(g.adj); }
         hp.iperm.assign(n, 0);
         for (int64_t i = 0; i < n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
@@ -494,6 +572,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
             hp.max_level_rows = std::max<int64_t>(hp.max_level_rows, hp.level_ptr[l + 1] - hp.level_ptr[l]);
         }
 
+        auto tr0 = std::chrono::steady_clock::now();
         // ---- renumbered matrix P A P^T -------------------------------------------------
         hp.rowptr.assign(n + 1, 0);
         for (int64_t r = 0; r < n; ++r) {
@@ -520,12 +599,14 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                 }
             }
         }
-
+        hp.phase_seconds[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tr0).count();
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");
     }
+    auto ts0 = std::chrono::steady_clock::now();
     st = build_schedule(hp, p, cache_bytes, opt);
     if (st != MPK_OK) return st;
+    hp.phase_seconds[3] = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
     hp.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return MPK_OK;
 }

@@ -102,7 +102,9 @@ class Plan:
     def info(self) -> dict:
         i = _lib.mpk_plan_info()
         check(lib().mpk_plan_query(self._h, ctypes.byref(i)))
-        return {name: getattr(i, name) for name, _ in i._fields_}
+        d = {name: getattr(i, name) for name, _ in i._fields_}
+        d["phase_seconds"] = list(d["phase_seconds"])
+        return d
 
     def arrays(self):
         inf = self.info()

@@ -1,0 +1,56 @@
+"""Autotuner / learned tuner.  CPU: configuration space and database
+integrity.  GPU: train the cost model with the library's MLP kernels on the
+MI355X sweep database, then compare its choices on held-out matrices with the
+exhaustive sweep's best and with the untuned default configuration."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2205_01598_amd import tune
+
+DB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                  "paper_2205_01598_amd", "data", "tuner_sweep_mi355x.jsonl")
+
+
+def test_config_grid():
+    grid = tune.config_grid()
+    assert grid[0] == tune.DEFAULT
+    keys = {json.dumps(c, sort_keys=True) for c in grid}
+    assert len(keys) == len(grid) == 1 + len(tune.CACHE_MB) * len(tune.SKEWS) * len(tune.TILES) * len(tune.GRIDS)
+    enc = np.stack([tune.encode_config(c) for c in grid])
+    assert np.all(np.isfinite(enc)) and len({tuple(e) for e in enc}) == len(grid)
+
+
+@pytest.mark.skipif(not os.path.exists(DB), reason="no sweep database")
+def test_database_integrity():
+    recs = tune.load_db(DB)
+    seeds = {r["seed"] for r in recs}
+    assert len(seeds) >= 100
+    fams = {r["spec"]["family"] for r in recs}
+    assert fams == {"stencil2d", "stencil3d", "banded", "zipf", "rgg"}
+    for r in recs:
+        assert r["ms"] > 0 and len(r["features"]) == 24
+    train, test = tune.split_seeds(recs)
+    assert {r["seed"] for r in train}.isdisjoint({r["seed"] for r in test})
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not os.path.exists(DB), reason="no sweep database")
+def test_learned_tuner_beats_default_on_held_out():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    recs = tune.load_db(DB)
+    train, test = tune.split_seeds(recs)
+    tuner = tune.LearnedTuner(hidden=64, seed=0)
+    loss = tuner.fit(train, steps=3000)
+    assert math.isfinite(loss)
+    m = tune.evaluate(tuner, test)
+    # the untuned default (C = 256 MB, grid = all resident workgroups) is
+    # measurably worse than the choice of the trained network
+    assert m["geomean_gain_over_default"] > 1.1, m
+    # and the choice is close to the exhaustive sweep's best
+    assert m["geomean_pick_over_best"] < 1.15, m

@@ -21,4 +21,5 @@ from .matrices import (  # noqa: F401
     random_phase_state,
     integer_stencil_27pt,
     random_small_csr,
+    tuner_matrix,
 )

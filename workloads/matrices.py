@@ -464,3 +464,64 @@ def random_phase_state(n: int, seed: int = 0) -> np.ndarray:
     out[:, 0] = np.cos(2 * np.pi * th) / np.sqrt(n)
     out[:, 1] = np.sin(2 * np.pi * th) / np.sqrt(n)
     return out
+
+
+# ----------------------------------------------------------------------------
+# tuner corpus
+# ----------------------------------------------------------------------------
+
+def _random_valued(csr: CSR, rng) -> CSR:
+    """Same pattern, values U[-1, 1] with a dominant diagonal (diagonal added
+    where missing)."""
+    n = csr.n
+    rows = np.repeat(np.arange(n), np.diff(csr.rowptr))
+    has_diag = np.zeros(n, bool)
+    has_diag[rows[csr.col == rows]] = True
+    if not has_diag.all():
+        miss = np.nonzero(~has_diag)[0]
+        rows = np.concatenate([rows, miss])
+        cols = np.concatenate([csr.col.astype(np.int64), miss])
+        order = np.lexsort((cols, rows))
+        rows, cols = rows[order], cols[order]
+        rowptr = np.zeros(n + 1, np.int64)
+        np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+        csr = CSR(n, rowptr, cols.astype(np.int32), np.zeros(rows.size))
+    vals = rng.uniform(-1.0, 1.0, size=csr.nnz)
+    return _dominant_diagonal(CSR(csr.n, csr.rowptr, csr.col, vals))
+
+
+def tuner_matrix(seed: int, n_min: float = 1e5, n_max: float = 1e6):
+    """One matrix of the learned-tuner corpus, chosen by the seed.
+
+    Families: 2D stencils (5, 9 points), 3D stencils (7, 13, 19, 27 points),
+    banded random (bandwidth log-uniform in [10, 1000]), power-law row lengths
+    (Zipf exponent in [1.5, 2.5], capped at 1024) and random geometric graphs;
+    N log-uniform in [n_min, n_max]; values U[-1, 1] with a dominant diagonal
+    (row-normalised weights for the geometric graphs).  Returns (CSR, spec).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 7919]))
+    fam = ["stencil2d", "stencil3d", "banded", "zipf", "rgg"][int(rng.integers(0, 5))]
+    N = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+    spec = {"seed": int(seed), "family": fam}
+    if fam == "stencil2d":
+        pts = int(rng.choice([5, 9]))
+        n = max(4, int(round(np.sqrt(N))))
+        A = _random_valued(stencil_2d(n, pts), rng)
+        spec.update(points=pts, grid=n)
+    elif fam == "stencil3d":
+        pts = int(rng.choice([7, 13, 19, 27]))
+        n = max(4, int(round(N ** (1.0 / 3.0))))
+        A = _random_valued(stencil_3d(n, pts), rng)
+        spec.update(points=pts, grid=n)
+    elif fam == "banded":
+        b = int(round(np.exp(rng.uniform(np.log(10), np.log(1000)))))
+        A = banded_random(N, b, seed=int(seed))
+        spec.update(bandwidth=b)
+    elif fam == "zipf":
+        s = float(rng.uniform(1.5, 2.5))
+        A = zipf_rows(N, s, seed=int(seed))
+        spec.update(exponent=round(s, 3))
+    else:
+        A, _ = random_geometric(N, 16.0, seed=int(seed))
+    spec.update(n=int(A.n), nnz=int(A.nnz))
+    return A, spec
