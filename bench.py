@@ -103,8 +103,13 @@ def bench_small_2d(torch, Plan, W, dev):
     tb = timed(torch, lambda: pl.run_baseline(X, Y), 200, 20)
     tm = timed(torch, lambda: pl.run(X, Y), 200, 20)
     pl.status()
+    G = pl.info()["n_groups"]
+    ladder = {"level_groups": G,
+              "launch_per_node_us": round(timed(torch, lambda: pl.run_sync(X, Y, "node"), 100, 10) * 1e3, 2),
+              "launch_per_wavefront_us": round(timed(torch, lambda: pl.run_sync(X, Y, "wavefront"), 100, 10) * 1e3, 2),
+              "p2p_flags_us": round(tm * 1e3, 2)}
     return {"workload": "5-point Laplacian 64^2, p=4", "mpk_us": round(tm * 1e3, 2),
-            "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3)}
+            "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3), "sync_ladder": ladder}
 
 
 def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
@@ -211,7 +216,7 @@ def bench_learned_tuner(torch, plan, X, Y, p, log):
     loss = tuner.fit(train, steps=3000)
     out = {"train_matrices": len({r["seed"] for r in train}), "held_out_matrices": len({r["seed"] for r in test}),
            "train_seconds": round(time.time() - t0, 2), "final_train_loss": round(loss, 5),
-           "held_out": tune.evaluate(tuner, test)}
+           "held_out": tune.evaluate(tuner, test, tune.best_static(train))}
     tune._apply(plan, p, tune.DEFAULT)
     feats = tune.plan_features(plan)
     t_def = tune.time_run(torch, plan, X, Y, reps=10)
@@ -316,6 +321,15 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"MPK p={p}: {ms:.3f} ms/step, {gflops:.1f} GFLOP/s, speedup {t_base / ms:.3f}")
 
+    # ---- synchronisation ladder on the same plan: kernel boundary per Lp node, per
+    # wavefront of independent nodes, then point-to-point flags (the timed MPK) ------
+    G = info["n_groups"]
+    ladder = {"level_groups": G, "launches": {"node": G * p, "wavefront": G + 2 * p - 2, "p2p_flags": 1},
+              "launch_per_node_ms": round(timed(torch, lambda: plan.run_sync(X, Y, "node"), 3, 1), 4),
+              "launch_per_wavefront_ms": round(timed(torch, lambda: plan.run_sync(X, Y, "wavefront"), 5, 1), 4),
+              "p2p_flags_ms": round(ms, 4), "baseline_ms": round(t_base, 4)}
+    log(f"sync ladder: {ladder}")
+
     # ---- other powers ----------------------------------------------------------------
     other = {}
     for q in (() if args.only_main else (4, 6)):
@@ -402,6 +416,7 @@ def main():
         "baseline_gflops": round(flop / t_base / 1e6, 1),
         "plan_seconds": round(plan_s, 2),
         "plan_spmv_equivalents": round(plan_s / (t_base / p * 1e-3), 0),
+        "sync_ladder": ladder,
         "other_powers": other,
         "mixed_precision": mixed,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -230,6 +230,23 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
 mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y,
                             const mpk_recurrence *rec, void *stream);
 
+/* Level-blocked MPK with bulk synchronisation instead of point-to-point
+ * flags (the variants Sec. 4.2 starts from before Sec. 4.3 replaces the
+ * barriers).  MPK_SYNC_NODE: one kernel launch per Lp node (level group i,
+ * power q) in the order of the plan's schedule (Fig. 6), G*p launches.
+ * MPK_SYNC_WAVEFRONT: one launch per wavefront w = i + 2q with all its
+ * nodes, G+2p-2 launches; node (i, q) reads groups i-1..i+1 at power q-1,
+ * which lie on wavefronts w-3..w-1, so the nodes of a launch are
+ * independent (a diagonal i + q of Fig. 6 is not: (i+1, q-1) feeds (i, q)).
+ * The kernel boundary on `stream` is the barrier.  Plain powers only (no
+ * recurrence); same arguments, layout and results as mpk_run, bit for bit,
+ * since every node uses the same chunks and the same arithmetic.  Errors:
+ * MPK_ERR_ARG for a bad granularity or buffer, MPK_ERR_STATE without upload,
+ * MPK_ERR_UNSUPPORTED for an nrhs/dtype combination without a kernel. */
+#define MPK_SYNC_NODE 0
+#define MPK_SYNC_WAVEFRONT 1
+mpk_status mpk_run_sync(mpk_plan *plan, const double *X, double *Y, int32_t granularity, void *stream);
+
 /* Waits for `stream` and reports whether the last mpk_run on this plan hit
  * the watchdog (MPK_ERR_TIMEOUT) or succeeded (MPK_OK). */
 mpk_status mpk_plan_status(mpk_plan *plan, void *stream);

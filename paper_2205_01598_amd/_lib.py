@@ -13,6 +13,8 @@ LIBPATH = os.path.join(HERE, "libmpk.so")
 
 MPK_MAX_POWER = 32
 MPK_MAX_NRHS = 32
+MPK_SYNC_NODE = 0
+MPK_SYNC_WAVEFRONT = 1
 MPK_NUM_FEATURES = 24
 
 STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_OOM", -4: "MPK_ERR_HIP",
@@ -82,6 +84,7 @@ SIGNATURES = {
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "mpk_run": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
     "mpk_run_baseline": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
+    "mpk_run_sync": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P]),
     "mpk_plan_status": (ctypes.c_int32, [_P, _P]),
     "mpk_plan_destroy": (None, [_P]),
     "spmv_create": (ctypes.c_int32, [ctypes.POINTER(mpk_csr), ctypes.POINTER(mpk_options),

@@ -7,15 +7,18 @@
 // chunks of at most chunk_nnz(k) stored nonzeros.  Phase 1: every thread
 // forms kProdPerThread of the chunk's k-column products (nonzero j, column c
 // flattened with c fastest), issuing all its val/col loads and then all its
-// gathers without waiting in between, and writes them to LDS.  Phase 2:
-// after a barrier, a thread sums one row's products (k <= 2: all columns of
-// the row; k >= 4: one column) in stored order and applies the epilogue.
+// gathers without waiting in between, and writes them to LDS together with
+// the chunk's row pointers.  Phase 2: after a barrier, a thread sums one
+// row's products (k <= 2: all columns of the row; k >= 4: one column) in
+// stored order, reading four products ahead, and applies the epilogue.  A
+// chunk is described by (first row, end row, first nonzero, end nonzero).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/mpk.h"
+#include "mpk_internal.h"
 
 namespace mpk {
 
@@ -72,12 +75,16 @@ constexpr int kProdPerThread = 8;  // products per thread and chunk
 // nonzeros per chunk for k right-hand sides: kBlock * kProdPerThread products
 // (16 KB of LDS in FP64) whatever k is
 __host__ __device__ constexpr int chunk_nnz(int K) { return kBlock * kProdPerThread / K; }
-constexpr int kChunkRows = 2048;  // rows per chunk cap (bounds the phase-2 loop)
-
 template <typename VT, int K>
 struct ChunkLds {
     typename AccumType<VT>::T prod[chunk_nnz(K) * K];
+    int32_t rb[kChunkRows + 1];  // row pointers of the chunk's rows
 };
+
+// Barrier for LDS only: each wavefront waits for its own LDS operations, then
+// the workgroup meets.  Unlike __syncthreads() it does not wait for
+// outstanding global loads, which stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Epilogue for one output row, all K columns held by the calling thread.
 template <int K, bool REC, bool COH>
@@ -114,10 +121,11 @@ __device__ __forceinline__ void store_row(int64_t r, const double *v_in, const d
     }
 }
 
-// One chunk: rows [r0, r1) whose stored nonzeros fit in chunk_nnz(K), or a
+// One chunk d = (r0, r1, j0, j1): rows [r0, r1) with stored nonzeros
+// [j0, j1), at most chunk_nnz(K) of them and at most kChunkRows rows, or a
 // single longer row.
 template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunk_pass(int r0, int r1, const int32_t *__restrict__ rowptr,
+__device__ __forceinline__ void chunk_pass(const int4 d, const int32_t *__restrict__ rowptr,
                                            const int32_t *__restrict__ col, const VT *__restrict__ val,
                                            const double *__restrict__ x, double *__restrict__ y, int q,
                                            const double *__restrict__ yq2, const RecArgs &rec,
@@ -126,7 +134,7 @@ __device__ __forceinline__ void chunk_pass(int r0, int r1, const int32_t *__rest
     constexpr int NP = kProdPerThread;
     static_assert(K == 1 || K == 2 || !REC, "the recurrence epilogue handles k <= 2");
     const int tid = threadIdx.x;
-    const int j0 = rowptr[r0], j1 = rowptr[r1];
+    const int r0 = d.x, r1 = d.y, j0 = d.z, j1 = d.w;
     if (j1 - j0 <= chunk_nnz(K)) {
         if (j1 == j0) {  // rows without stored entries: y = 0 (uniform branch)
             for (int r = r0 + tid; r < r1; r += kBlock) {
@@ -142,6 +150,13 @@ __device__ __forceinline__ void chunk_pass(int r0, int r1, const int32_t *__rest
             }
             return;
         }
+        const int nr = r1 - r0;
+        // row pointers rowptr[r0 .. r1] (uniform guards: no divergence)
+        constexpr int NRB = (kChunkRows + 1 + kBlock - 1) / kBlock;
+        int rbv[NRB];
+#pragma unroll
+        for (int m = 0; m < NRB; ++m)
+            if (m * kBlock <= nr) rbv[m] = rowptr[r0 + min(tid + m * kBlock, nr)];
         // phase 1: every load is unconditional (slots past the chunk re-read
         // its last entry, whose product phase 2 never reads), so a thread
         // issues all its val/col loads, then all its gathers, without waiting
@@ -155,43 +170,64 @@ __device__ __forceinline__ void chunk_pass(int r0, int r1, const int32_t *__rest
             cj[m] = col[jc];
             a[m] = (AT)load_value(val, jc);
         }
-        // row bounds of the thread's first phase-2 output, fetched early
-        const int rf = min(r0 + (K <= 2 ? tid : tid / K), r1);
-        const int rs0 = rowptr[rf], re0 = rowptr[min(rf + 1, r1)];
         AT xv[NP];
 #pragma unroll
         for (int m = 0; m < NP; ++m) xv[m] = (AT)x[(int64_t)cj[m] * K + ((tid + m * kBlock) % K)];
 #pragma unroll
+        for (int m = 0; m < NRB; ++m)
+            if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = rbv[m];
+#pragma unroll
         for (int m = 0; m < NP; ++m) lds.prod[tid + m * kBlock] = a[m] * xv[m];
-        __syncthreads();
+        lds_barrier();
         if constexpr (K <= 2) {
             // phase 2: one thread per row, all K columns, stored order
-            for (int r = r0 + tid; r < r1; r += kBlock) {
-                const int s = (r == rf ? rs0 : rowptr[r]) - j0, e = (r == rf ? re0 : rowptr[r + 1]) - j0;
+            for (int r = tid; r < nr; r += kBlock) {
+                const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
                 AT sum[K];
 #pragma unroll
                 for (int c = 0; c < K; ++c) sum[c] = (AT)0;
-                for (int i = s; i < e; ++i) {
+                int i = s;
+                for (; i + 4 <= e; i += 4) {
+                    AT pr[4][K];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int c = 0; c < K; ++c) pr[u][c] = lds.prod[(i + u) * K + c];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int c = 0; c < K; ++c) sum[c] = sum[c] + pr[u][c];
+                }
+                for (; i < e; ++i) {
 #pragma unroll
                     for (int c = 0; c < K; ++c) sum[c] = sum[c] + lds.prod[i * K + c];
                 }
                 double v[K];
 #pragma unroll
                 for (int c = 0; c < K; ++c) v[c] = (double)sum[c];
-                store_row<K, REC, COH>(r, v, x, y, q, yq2, rec);
+                store_row<K, REC, COH>(r0 + r, v, x, y, q, yq2, rec);
             }
         } else {
             // phase 2: one thread per (row, column), stored order
-            const int nout = (r1 - r0) * K;
+            const int nout = nr * K;
             for (int o = tid; o < nout; o += kBlock) {
-                const int r = r0 + o / K, c = o % K;
-                const int s = (r == rf ? rs0 : rowptr[r]) - j0, e = (r == rf ? re0 : rowptr[r + 1]) - j0;
+                const int r = o / K, c = o % K;
+                const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
                 AT sum = (AT)0;
-                for (int i = s; i < e; ++i) sum = sum + lds.prod[i * K + c];
-                put<COH>(y + (int64_t)r * K + c, (double)sum);
+                int i = s;
+                for (; i + 4 <= e; i += 4) {
+                    const AT p0 = lds.prod[i * K + c], p1 = lds.prod[(i + 1) * K + c];
+                    const AT p2 = lds.prod[(i + 2) * K + c], p3 = lds.prod[(i + 3) * K + c];
+                    sum = sum + p0;
+                    sum = sum + p1;
+                    sum = sum + p2;
+                    sum = sum + p3;
+                }
+                for (; i < e; ++i) sum = sum + lds.prod[i * K + c];
+                put<COH>(y + (int64_t)(r0 + r) * K + c, (double)sum);
             }
         }
-        __syncthreads();  // LDS is reused by the next chunk
+        lds_barrier();  // LDS is reused by the next chunk
     } else {
         // a single row longer than a chunk: thread (slot, c) accumulates
         // nonzeros slot, slot + S, ... of column c; then a tree over slots

@@ -51,7 +51,7 @@ struct mpk_plan {
     void *d_val = nullptr;
     int32_t *d_tile_row = nullptr, *d_work = nullptr;
     int32_t *d_perm = nullptr;
-    int32_t *d_chunk_row = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;
+    int32_t *d_chunk = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;  // d_chunk: int4 per chunk
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
     std::vector<void *> allocs;
 };
@@ -60,7 +60,7 @@ struct mpk_spmv {
     int64_t n = 0, nnz = 0;
     int32_t dtype = MPK_F64, nrhs = 1;
     int64_t nchunks = 0;
-    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_chunk_row = nullptr;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_chunk = nullptr;
     void *d_val = nullptr;
     std::vector<void *> allocs;
 };
@@ -78,6 +78,20 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kStripeBase = 64;
 constexpr int kStripeStride = 64;
 constexpr int kCtrlWords = kStripeBase + kMaxStripes * kStripeStride;
+
+// Device chunk table: (first row, end row, first nonzero, end nonzero) per
+// chunk, from the chunk start rows and the row pointers.
+std::vector<int32_t> chunk_descriptors(const std::vector<int32_t> &chunk_row, const int32_t *rowptr) {
+    const size_t nc = chunk_row.empty() ? 0 : chunk_row.size() - 1;
+    std::vector<int32_t> d(4 * nc);
+    for (size_t c = 0; c < nc; ++c) {
+        d[4 * c + 0] = chunk_row[c];
+        d[4 * c + 1] = chunk_row[c + 1];
+        d[4 * c + 2] = rowptr[chunk_row[c]];
+        d[4 * c + 3] = rowptr[chunk_row[c + 1]];
+    }
+    return d;
+}
 
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
@@ -134,29 +148,60 @@ void convert_values(const double *src, size_t n, int32_t dtype, std::vector<uint
 
 // Rows of chunks [c0, c1), one chunk after another.
 template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunks_body(int c0, int c1, const int32_t *__restrict__ chunk_row,
+__device__ __forceinline__ void chunks_body(int c0, int c1, const int4 *__restrict__ chunk,
                                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                             const VT *__restrict__ val, const double *__restrict__ x,
                                             double *__restrict__ y, int q, const double *__restrict__ yq2,
                                             const RecArgs &rec) {
     __shared__ ChunkLds<VT, K> lds;
     for (int c = c0; c < c1; ++c)
-        chunk_pass<VT, K, REC, COH>(chunk_row[c], chunk_row[c + 1], rowptr, col, val, x, y, q, yq2, rec, lds);
+        chunk_pass<VT, K, REC, COH>(chunk[c], rowptr, col, val, x, y, q, yq2, rec, lds);
 }
 
 // Baseline SpMV: one workgroup per chunk.
 template <typename VT, int K, bool REC>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(const int32_t *__restrict__ chunk_row,
+__global__ __launch_bounds__(kBlock) void spmv_kernel(const int4 *__restrict__ chunk,
                                                       const int32_t *__restrict__ rowptr,
                                                       const int32_t *__restrict__ col,
                                                       const VT *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y, int q,
                                                       const double *__restrict__ yq2, RecArgs rec) {
-    chunks_body<VT, K, REC, false>(blockIdx.x, blockIdx.x + 1, chunk_row, rowptr, col, val, x, y, q, yq2, rec);
+    chunks_body<VT, K, REC, false>(blockIdx.x, blockIdx.x + 1, chunk, rowptr, col, val, x, y, q, yq2, rec);
+}
+
+// Bulk-synchronous level-blocked MPK: one launch computes a list of Lp
+// nodes (a level group's chunks at one power).  Workgroup b takes chunk
+// b - start[s] of segment s.  With one node per launch, or one wavefront of
+// independent nodes per launch, the kernel boundary is the barrier between
+// dependent nodes (the variants without point-to-point synchronisation,
+// Sec. 4.2).
+constexpr int kMaxSegments = MPK_MAX_POWER;
+struct SegList {
+    int32_t n;
+    int32_t start[kMaxSegments + 1];  // workgroup offset of each segment
+    int32_t c0[kMaxSegments];         // first chunk
+    int32_t q[kMaxSegments];          // power
+};
+
+template <typename VT, int K>
+__global__ __launch_bounds__(kBlock) void segment_kernel(SegList L, const int4 *__restrict__ chunk,
+                                                         const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const VT *__restrict__ val, const double *__restrict__ X,
+                                                         double *__restrict__ Y, int64_t NK) {
+    const int b = blockIdx.x;
+    int s = 0;
+    while (s + 1 < L.n && L.start[s + 1] <= b) ++s;
+    const int c = L.c0[s] + (b - L.start[s]);
+    const int q = L.q[s];
+    const double *x = q == 1 ? X : Y + (int64_t)(q - 2) * NK;
+    double *y = Y + (int64_t)(q - 1) * NK;
+    RecArgs none{};
+    chunks_body<VT, K, false, false>(c, c + 1, chunk, rowptr, col, val, x, y, q, nullptr, none);
 }
 
 struct MpkArgs {
-    const int32_t *chunk_row;
+    const int4 *chunk;
     const int32_t *tile_chunk;
     const int32_t *rowptr;
     const int32_t *col;
@@ -270,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
-        chunks_body<VT, K, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk_row, a.rowptr, a.col,
+        chunks_body<VT, K, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk, a.rowptr, a.col,
                                       val, xin, yout, q, yq2, rec);
         // The next ticket is taken only now: a workgroup never holds a ticket
         // it is not working on, so no ticket waits behind an idle one.
@@ -336,12 +381,22 @@ __global__ __launch_bounds__(kBlock) void bw_probe(const double2 *__restrict__ b
 
 template <typename VT, int K, bool REC>
 struct Dispatch {
-    static hipError_t spmv(int blocks, hipStream_t s, const int32_t *chunks, const int32_t *rp, const int32_t *ci,
+    static hipError_t spmv(int blocks, hipStream_t s, const int4 *chunks, const int32_t *rp, const int32_t *ci,
                            const void *v, const double *x, double *y, int q, const double *yq2,
                            const RecArgs &rec) {
         hipLaunchKernelGGL((spmv_kernel<VT, K, REC>), dim3(blocks), dim3(kBlock), 0, s, chunks, rp, ci,
                            reinterpret_cast<const VT *>(v), x, y, q, yq2, rec);
         return hipGetLastError();
+    }
+    static hipError_t seg(int blocks, hipStream_t s, const SegList &L, const int4 *chunks, const int32_t *rp,
+                          const int32_t *ci, const void *v, const double *X, double *Y, int64_t NK) {
+        if constexpr (REC) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((segment_kernel<VT, K>), dim3(blocks), dim3(kBlock), 0, s, L, chunks, rp, ci,
+                               reinterpret_cast<const VT *>(v), X, Y, NK);
+            return hipGetLastError();
+        }
     }
     static hipError_t mpk(int blocks, hipStream_t s, const MpkArgs &a, const RecArgs &rec) {
         hipLaunchKernelGGL((mpk_persistent<VT, K, REC>), dim3(blocks), dim3(kBlock), 0, s, a, rec);
@@ -605,7 +660,8 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
     if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
     if ((e = dev_alloc(al, &plan->d_perm, h.n, &bytes)) != hipSuccess) return cleanup_fail(e, "perm");
-    if ((e = dev_alloc(al, &plan->d_chunk_row, h.chunk_row.size(), &bytes)) != hipSuccess)
+    const std::vector<int32_t> desc = chunk_descriptors(h.chunk_row, h.rowptr.data());
+    if ((e = dev_alloc(al, &plan->d_chunk, std::max<size_t>(desc.size(), 4), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
     if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
@@ -617,7 +673,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
         {plan->d_work, h.work_streams.data(), sizeof(int32_t) * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
-        {plan->d_chunk_row, h.chunk_row.data(), sizeof(int32_t) * h.chunk_row.size()},
+        {plan->d_chunk, desc.data(), sizeof(int32_t) * desc.size()},
         {plan->d_tile_chunk, h.tile_chunk.data(), sizeof(int32_t) * h.tile_chunk.size()},
     };
     for (auto &c : cps)
@@ -688,7 +744,7 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     plan->epoch += 1;
     if (plan->epoch == 0) plan->epoch = 1;
     MpkArgs a;
-    a.chunk_row = plan->d_chunk_row;
+    a.chunk = reinterpret_cast<const int4 *>(plan->d_chunk);
     a.tile_chunk = plan->d_tile_chunk;
     a.rowptr = plan->d_rowptr;
     a.col = plan->d_col;
@@ -734,10 +790,67 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
         hipError_t e = dispatch_all(h.opt.val_dtype, K, rec != nullptr, [&](auto d) {
-            return decltype(d)::spmv(blocks, s, plan->d_chunk_row, plan->d_rowptr, plan->d_col, plan->d_val, x, y,
+            return decltype(d)::spmv(blocks, s, reinterpret_cast<const int4 *>(plan->d_chunk), plan->d_rowptr,
+                                     plan->d_col, plan->d_val, x, y,
                                      q, yq2, ra);
         });
         if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));
+    }
+    return MPK_OK;
+}
+
+mpk_status mpk_run_sync(mpk_plan *plan, const double *X, double *Y, int32_t granularity, void *stream) {
+    mpk_status st = check_run_args(plan, X, Y);
+    if (st != MPK_OK) return st;
+    if (granularity != MPK_SYNC_NODE && granularity != MPK_SYNC_WAVEFRONT)
+        return fail(MPK_ERR_ARG, "granularity must be MPK_SYNC_NODE or MPK_SYNC_WAVEFRONT");
+    HostPlan &h = plan->hp;
+    if (h.n == 0) return MPK_OK;
+    if (!supported(h.opt.val_dtype, h.opt.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
+    const int K = h.opt.nrhs;
+    const int64_t NK = h.n * K;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int32_t G = (int32_t)h.group_ptr.size() - 1, P = h.p;
+    SegList L;
+    L.n = 0;
+    L.start[0] = 0;
+    auto add = [&](int32_t g, int32_t q) {
+        const int32_t c0 = h.tile_chunk[h.group_tile[g]], c1 = h.tile_chunk[h.group_tile[g + 1]];
+        L.c0[L.n] = c0;
+        L.q[L.n] = q;
+        L.start[L.n + 1] = L.start[L.n] + (c1 - c0);
+        ++L.n;
+    };
+    auto flush = [&]() -> mpk_status {
+        const int blocks = L.n ? L.start[L.n] : 0;
+        if (blocks > 0) {
+            hipError_t e = dispatch_all(h.opt.val_dtype, K, false, [&](auto d) {
+                return decltype(d)::seg(blocks, s, L, reinterpret_cast<const int4 *>(plan->d_chunk), plan->d_rowptr,
+                                        plan->d_col, plan->d_val, X, Y, NK);
+            });
+            if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("segment launch: ") + hipGetErrorString(e));
+        }
+        L.n = 0;
+        return MPK_OK;
+    };
+    if (granularity == MPK_SYNC_NODE) {
+        // the Lp schedule, one node per launch
+        const int64_t nodes = (int64_t)h.schedule.size() / 3;
+        for (int64_t k = 0; k < nodes; ++k) {
+            add(h.schedule[3 * k + 2], h.schedule[3 * k + 1]);
+            if ((st = flush()) != MPK_OK) return st;
+        }
+        return MPK_OK;
+    }
+    // wavefronts w = g + 2q: node (g, q) needs groups g-1..g+1 at power q-1,
+    // whose wavefronts are w-3..w-1, so the nodes of one wavefront are
+    // independent and a launch per wavefront respects every dependency
+    for (int32_t w = 2; w <= G - 1 + 2 * P; ++w) {
+        for (int32_t q = 1; q <= P; ++q) {
+            const int32_t g = w - 2 * q;
+            if (g >= 0 && g < G) add(g, q);
+        }
+        if ((st = flush()) != MPK_OK) return st;
     }
     return MPK_OK;
 }
@@ -781,9 +894,10 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
     std::vector<int32_t> chunks;
-    append_chunks(rp, 0, A->n, chunk_nnz_host(o.nrhs), 2048, chunks);
+    append_chunks(rp, 0, A->n, chunk_nnz_host(o.nrhs), kChunkRows, chunks);
     chunks.push_back((int32_t)A->n);
     h->nchunks = (int64_t)chunks.size() - 1;
+    const std::vector<int32_t> desc = chunk_descriptors(chunks, rp.data());
     std::vector<uint8_t> vbuf;
     convert_values(A->val, A->nnz, o.val_dtype, vbuf);
     hipError_t e;
@@ -791,7 +905,7 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     if ((e = dev_alloc(h->allocs, &h->d_rowptr, A->n + 1)) != hipSuccess ||
         (e = dev_alloc(h->allocs, &h->d_col, A->nnz)) != hipSuccess ||
         (e = dev_alloc(h->allocs, &dv, vbuf.size())) != hipSuccess ||
-        (e = dev_alloc(h->allocs, &h->d_chunk_row, chunks.size())) != hipSuccess) {
+        (e = dev_alloc(h->allocs, &h->d_chunk, std::max<size_t>(desc.size(), 4))) != hipSuccess) {
         free_all(h->allocs);
         delete h;
         return fail(e == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP, hipGetErrorString(e));
@@ -803,8 +917,8 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
                        hipSuccess) ||
         (A->nnz && (e = hipMemcpy(h->d_val, vbuf.data(), A->nnz * value_bytes(o.val_dtype),
                                   hipMemcpyHostToDevice)) != hipSuccess) ||
-        (e = hipMemcpy(h->d_chunk_row, chunks.data(), sizeof(int32_t) * chunks.size(),
-                       hipMemcpyHostToDevice)) != hipSuccess) {
+        (!desc.empty() && (e = hipMemcpy(h->d_chunk, desc.data(), sizeof(int32_t) * desc.size(),
+                                         hipMemcpyHostToDevice)) != hipSuccess)) {
         free_all(h->allocs);
         delete h;
         return fail(MPK_ERR_HIP, hipGetErrorString(e));
@@ -817,7 +931,8 @@ static mpk_status spmv_launch(mpk_spmv *h, const double *x, double *y, hipStream
     RecArgs ra;
     (void)fill_rec(nullptr, 1, h->nrhs, ra);
     hipError_t e = dispatch_all(h->dtype, h->nrhs, false, [&](auto d) {
-        return decltype(d)::spmv((int)h->nchunks, s, h->d_chunk_row, h->d_rowptr, h->d_col, h->d_val, x, y, 1,
+        return decltype(d)::spmv((int)h->nchunks, s, reinterpret_cast<const int4 *>(h->d_chunk), h->d_rowptr,
+                                 h->d_col, h->d_val, x, y, 1,
                                  nullptr, ra);
     });
     if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("spmv launch: ") + hipGetErrorString(e));

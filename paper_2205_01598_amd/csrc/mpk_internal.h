@@ -90,6 +90,8 @@ void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_
 
 // Nonzeros per kernel chunk for k right-hand sides (matches the device code).
 int32_t chunk_nnz_host(int32_t k);
+// rows per chunk cap: bounds the chunk's row-pointer slice kept in LDS
+constexpr int32_t kChunkRows = 1024;
 
 // Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
 int32_t bytes_per_nnz(int32_t dtype);

@@ -13,6 +13,8 @@
 #include <limits>
 #include <numeric>
 
+#include <omp.h>
+
 #include "mpk_internal.h"
 
 namespace mpk {
@@ -90,35 +92,85 @@ struct Graph {
     int64_t deg(int64_t u) const { return ptr[u + 1] - ptr[u]; }
 };
 
+// Undirected graph of the pattern of A + A^T without the diagonal; every
+// adjacency list ascending and free of duplicates.  A pattern that is already
+// symmetric (checked by binary search, rows sorted) is taken as is; otherwise
+// the transpose is formed and merged with A.
 void build_graph(const mpk_csr *A, Graph &g) {
     const int64_t n = A->n;
-    // transpose by counting sort; walking rows in order leaves every
-    // transposed row sorted
-    std::vector<int64_t> tptr(n + 1, 0);
-    for (int64_t j = 0; j < A->nnz; ++j) tptr[A->col[j] + 1]++;
-    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
-    std::vector<int32_t> tadj(std::max<int64_t>(A->nnz, 1));
-    {
-        std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
-        for (int64_t r = 0; r < n; ++r)
-            for (int64_t j = A->rowptr[r]; j < A->rowptr[r + 1]; ++j) tadj[pos[A->col[j]]++] = (int32_t)r;
+    const int64_t *rp = A->rowptr;
+    const int32_t *ci = A->col;
+    bool sorted = true;
+#pragma omp parallel for schedule(dynamic, 8192) reduction(&& : sorted)
+    for (int64_t u = 0; u < n; ++u) sorted = sorted && std::is_sorted(ci + rp[u], ci + rp[u + 1]);
+    bool symmetric = sorted;
+    if (sorted) {
+#pragma omp parallel for schedule(dynamic, 8192) reduction(&& : symmetric)
+        for (int64_t u = 0; u < n; ++u) {
+            if (!symmetric) continue;
+            for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+                const int32_t v = ci[j];
+                if (v == u) continue;
+                if (!std::binary_search(ci + rp[v], ci + rp[v + 1], (int32_t)u)) {
+                    symmetric = false;
+                    break;
+                }
+            }
+        }
     }
-    // rows of A, sorted copies where needed
-    std::vector<int32_t> rowbuf;
-    g.ptr.assign(n + 1, 0);
-    // upper bound of each merged list, then compact after merging
-    std::vector<int64_t> ub(n + 1, 0);
-    for (int64_t u = 0; u < n; ++u)
-        ub[u + 1] = ub[u] + (A->rowptr[u + 1] - A->rowptr[u]) + (tptr[u + 1] - tptr[u]);
-    std::vector<int32_t> tmp(std::max<int64_t>(ub[n], 1));
     std::vector<int64_t> len(n, 0);
+    g.ptr.assign(n + 1, 0);
+    if (symmetric) {
+        auto emit = [&](int64_t u, int32_t *o) {
+            int64_t m = 0, last = -1;
+            for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+                const int32_t v = ci[j];
+                if (v == u || v == last) continue;
+                if (o) o[m] = v;
+                ++m;
+                last = v;
+            }
+            return m;
+        };
+#pragma omp parallel for schedule(dynamic, 8192)
+        for (int64_t u = 0; u < n; ++u) len[u] = emit(u, nullptr);
+        for (int64_t u = 0; u < n; ++u) g.ptr[u + 1] = g.ptr[u] + len[u];
+        g.adj.resize(std::max<int64_t>(g.ptr[n], 1));
+#pragma omp parallel for schedule(dynamic, 8192)
+        for (int64_t u = 0; u < n; ++u) emit(u, g.adj.data() + g.ptr[u]);
+        return;
+    }
+    // transpose by counting sort; each thread owns a range of columns and
+    // walks the rows in order, so every transposed row comes out sorted
+    std::vector<int64_t> tptr(n + 1, 0);
+    std::vector<int32_t> tadj(std::max<int64_t>(A->nnz, 1));
+#pragma omp parallel
+    {
+        const int T = omp_get_num_threads(), t = omp_get_thread_num();
+        const int64_t c0 = n * t / T, c1 = n * (t + 1) / T;
+        for (int64_t j = 0; j < A->nnz; ++j)
+            if (ci[j] >= c0 && ci[j] < c1) tptr[ci[j] + 1]++;
+#pragma omp barrier
+#pragma omp single
+        for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+        std::vector<int64_t> pos(tptr.begin() + c0, tptr.begin() + c1);
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t j = rp[r]; j < rp[r + 1]; ++j) {
+                const int32_t c = ci[j];
+                if (c >= c0 && c < c1) tadj[pos[c - c0]++] = (int32_t)r;
+            }
+    }
+    // merge row u of A (sorted copy where needed) with row u of A^T
+    std::vector<int64_t> ub(n + 1, 0);
+    for (int64_t u = 0; u < n; ++u) ub[u + 1] = ub[u] + (rp[u + 1] - rp[u]) + (tptr[u + 1] - tptr[u]);
+    std::vector<int32_t> tmp(std::max<int64_t>(ub[n], 1));
 #pragma omp parallel
     {
         std::vector<int32_t> rb;
 #pragma omp for schedule(dynamic, 4096)
         for (int64_t u = 0; u < n; ++u) {
-            const int32_t *ra = A->col + A->rowptr[u];
-            int64_t na = A->rowptr[u + 1] - A->rowptr[u];
+            const int32_t *ra = ci + rp[u];
+            int64_t na = rp[u + 1] - rp[u];
             if (!std::is_sorted(ra, ra + na)) {
                 rb.assign(ra, ra + na);
                 std::sort(rb.begin(), rb.end());
@@ -147,47 +199,104 @@ void build_graph(const mpk_csr *A, Graph &g) {
         std::memcpy(g.adj.data() + g.ptr[u], tmp.data() + ub[u], sizeof(int32_t) * len[u]);
 }
 
-// Distances from root inside its component; returns the eccentricity.
-int64_t bfs_distance(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &dist,
-                     std::vector<int32_t> &queue) {
-    std::fill(dist.begin(), dist.end(), -1);
-    int64_t head = 0, tail = 0;
-    dist[root] = 0;
-    queue[tail++] = (int32_t)root;
-    int32_t far = 0;
-    while (head < tail) {
-        int32_t u = queue[head++];
-        int32_t du = dist[u];
-        for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
-            int32_t v = g.adj[j];
-            if (dist[v] < 0) {
-                dist[v] = du + 1;
-                far = du + 1;
-                queue[tail++] = v;
+// Breadth-first levels of one component (Eq. 3) in Cuthill-McKee discovery
+// order: each vertex of level i, taken in new order, appends its not yet
+// numbered neighbours in ascending original index.  `order` receives the
+// component from position `start` on; `owner[v]` must be INT32_MAX for every
+// vertex not yet numbered and holds a position below `start` otherwise.
+// Level boundaries are appended to `lptr` (the first entry, `start`, is the
+// caller's).  Returns the position after the component.
+//
+// A large frontier is expanded in parallel with the same result as the
+// queue: owner[v] = smallest frontier position adjacent to v (atomic
+// minimum), then each frontier vertex writes the neighbours it owns, in
+// adjacency order, at the prefix sum of the owned counts.
+constexpr int64_t kParallelFrontier = 2048;
+
+int64_t bfs_component(const Graph &g, int64_t root, int64_t start, std::vector<int32_t> &order,
+                      std::vector<int32_t> &owner, std::vector<int32_t> &lptr, std::vector<int64_t> &cnt) {
+    order[start] = (int32_t)root;
+    owner[root] = -1;
+    int64_t a = start, b = start + 1;
+    while (a < b) {
+        int64_t tail = b;
+        const int64_t F = b - a;
+        if (F < kParallelFrontier) {
+            for (int64_t f = a; f < b; ++f) {
+                const int32_t u = order[f];
+                for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+                    const int32_t v = g.adj[j];
+                    if (owner[v] == INT32_MAX) {
+                        owner[v] = (int32_t)f;
+                        order[tail++] = v;
+                    }
+                }
             }
+        } else {
+            if ((int64_t)cnt.size() < F + 1) cnt.resize(F + 1);
+            int32_t *own = owner.data();
+#pragma omp parallel for schedule(dynamic, 256)
+            for (int64_t f = a; f < b; ++f) {
+                const int32_t u = order[f];
+                for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+                    int32_t *w = own + g.adj[j];
+                    int32_t cur = __atomic_load_n(w, __ATOMIC_RELAXED);
+                    while (cur > (int32_t)f &&
+                           !__atomic_compare_exchange_n(w, &cur, (int32_t)f, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+                    }
+                }
+            }
+#pragma omp parallel for schedule(dynamic, 256)
+            for (int64_t f = a; f < b; ++f) {
+                const int32_t u = order[f];
+                int64_t c = 0;
+                for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) c += owner[g.adj[j]] == (int32_t)f;
+                cnt[f - a + 1] = c;
+            }
+            cnt[0] = 0;
+            for (int64_t i = 0; i < F; ++i) cnt[i + 1] += cnt[i];
+#pragma omp parallel for schedule(dynamic, 256)
+            for (int64_t f = a; f < b; ++f) {
+                const int32_t u = order[f];
+                int64_t o = b + cnt[f - a];
+                for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+                    const int32_t v = g.adj[j];
+                    if (owner[v] == (int32_t)f) order[o++] = v;
+                }
+            }
+            tail = b + cnt[F];
         }
+        lptr.push_back((int32_t)b);
+        a = b;
+        b = tail;
     }
-    return far;
+    return a;
 }
 
 // George-Liu pseudo-peripheral search from `start`: move to the
 // smallest-degree vertex (lowest index on ties) of the farthest level while
 // that raises the eccentricity.
 int64_t peripheral_root(const Graph &g, int64_t n, int64_t start) {
-    std::vector<int32_t> dist(n), queue(n);
+    std::vector<int32_t> order(n), owner(n), lptr;
+    std::vector<int64_t> cnt;
+    auto sweep = [&](int64_t r) {
+        std::fill(owner.begin(), owner.end(), INT32_MAX);
+        lptr.assign(1, 0);
+        bfs_component(g, r, 0, order, owner, lptr, cnt);
+        return (int64_t)lptr.size() - 2;  // eccentricity = levels - 1
+    };
     int64_t r = start;
-    int64_t ecc = bfs_distance(g, n, r, dist, queue);
+    int64_t ecc = sweep(r);
     for (;;) {
         int64_t best = -1, bestdeg = 0;
-        for (int64_t v = 0; v < n; ++v) {
-            if (dist[v] != ecc) continue;
-            int64_t d = g.deg(v);
-            if (best < 0 || d < bestdeg) {
+        for (int64_t i = lptr[lptr.size() - 2]; i < lptr.back(); ++i) {
+            const int64_t v = order[i], d = g.deg(v);
+            if (best < 0 || d < bestdeg || (d == bestdeg && v < best)) {
                 best = v;
                 bestdeg = d;
             }
         }
-        int64_t e2 = bfs_distance(g, n, best, dist, queue);
+        const int64_t e2 = sweep(best);
         if (e2 > ecc) {
             r = best;
             ecc = e2;
@@ -197,41 +306,20 @@ int64_t peripheral_root(const Graph &g, int64_t n, int64_t start) {
     }
 }
 
-// Queue BFS (Eq. 3).  The queue order is the new numbering: each vertex of
-// level i, taken in new order, appends its not yet numbered neighbours in
-// ascending original index, so level i+1 comes out contiguous and in
-// discovery order.  An empty frontier with vertices left starts the next
-// level at the smallest unnumbered original index.
+// Levels of the whole graph: the root's component first, then each further
+// component from its smallest unnumbered original index, at the next level.
 void bfs_levels(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &perm,
                 std::vector<int32_t> &level_ptr) {
     perm.assign(n, 0);
-    level_ptr.clear();
-    level_ptr.push_back(0);
+    level_ptr.assign(1, 0);
     if (n == 0) return;
-    std::vector<uint8_t> seen(n, 0);
-    int64_t tail = 0, head = 0, scan = 0;
-    perm[tail++] = (int32_t)root;
-    seen[root] = 1;
-    int64_t level_end = tail;
-    while (head < n) {
-        if (head == tail) {  // frontier exhausted: next component, own level
-            while (seen[scan]) ++scan;
-            perm[tail++] = (int32_t)scan;
-            seen[scan] = 1;
-            level_end = tail;
-        }
-        int32_t u = perm[head++];
-        for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
-            int32_t v = g.adj[j];
-            if (!seen[v]) {
-                seen[v] = 1;
-                perm[tail++] = v;
-            }
-        }
-        if (head == level_end) {
-            level_ptr.push_back((int32_t)head);
-            level_end = tail;
-        }
+    std::vector<int32_t> owner(n, INT32_MAX);
+    std::vector<int64_t> cnt;
+    int64_t pos = bfs_component(g, root, 0, perm, owner, level_ptr, cnt);
+    int64_t scan = 0;
+    while (pos < n) {
+        while (owner[scan] != INT32_MAX) ++scan;
+        pos = bfs_component(g, scan, pos, perm, owner, level_ptr, cnt);
     }
 }
 
@@ -397,7 +485,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         const int64_t cnz = chunk_nnz_host(opt.nrhs);
         for (int64_t t = 0; t < T; ++t) {
             hp.tile_chunk[t] = (int32_t)hp.chunk_row.size();
-            append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, 2048, hp.chunk_row);
+            append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, kChunkRows, hp.chunk_row);
         }
         hp.tile_chunk[T] = (int32_t)hp.chunk_row.size();
         hp.chunk_row.push_back((int32_t)n);

@@ -160,6 +160,14 @@ class Plan:
         check(lib().mpk_run_baseline(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
         return Y
 
+    def run_sync(self, X, Y, granularity: str = "wavefront", stream=None):
+        """Level-blocked MPK with a kernel launch per Lp node ("node") or per
+        wavefront of independent nodes ("wavefront") instead of
+        point-to-point flags."""
+        g = {"node": 0, "wavefront": 1}[granularity]
+        check(lib().mpk_run_sync(self._h, _ptr(X), _ptr(Y), g, _stream(stream)))
+        return Y
+
     def status(self, stream=None):
         check(lib().mpk_plan_status(self._h, _stream(stream)))
 

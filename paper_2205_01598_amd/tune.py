@@ -306,10 +306,25 @@ class LearnedTuner:
         return configs[int(np.argmin(pred))]
 
 
-def evaluate(tuner: LearnedTuner, records):
+def best_static(records):
+    """The one configuration with the smallest geometric-mean time relative
+    to the default over the given records (the tuner without features)."""
+    keys = [json.dumps(c, sort_keys=True) for c in config_grid()]
+    logs = {k: [] for k in keys}
+    for g in _group(records).values():
+        t = {json.dumps(r["config"], sort_keys=True): r["ms"] for r in g}
+        tdef = t[json.dumps(DEFAULT, sort_keys=True)]
+        for k in keys:
+            logs[k].append(math.log(t[k] / tdef))
+    best = min(keys, key=lambda k: np.mean(logs[k]))
+    return json.loads(best)
+
+
+def evaluate(tuner: LearnedTuner, records, static=None):
     """Held-out quality: the measured time of the chosen configuration against
-    the sweep's best and the untuned default, per (matrix, p)."""
-    ratios, gains, within = [], [], 0
+    the sweep's best, the untuned default and (if given) one static
+    configuration, per (matrix, p)."""
+    ratios, gains, within, sgains = [], [], 0, []
     groups = _group(records)
     for g in groups.values():
         cfg = tuner.choose(g[0]["features"], [r["config"] for r in g])
@@ -320,11 +335,48 @@ def evaluate(tuner: LearnedTuner, records):
         ratios.append(tpick / tbest)
         gains.append(tdef / tpick)
         within += tpick <= 1.05 * tbest
+        if static is not None:
+            sgains.append(tdef / t[json.dumps(static, sort_keys=True)])
     n = len(groups)
-    return {"cases": n,
-            "geomean_pick_over_best": float(np.exp(np.mean(np.log(ratios)))),
-            "within_5pct_of_best": within / max(n, 1),
-            "geomean_gain_over_default": float(np.exp(np.mean(np.log(gains)))),
-            "geomean_best_over_default": float(np.exp(np.mean(np.log(
-                [min(r["ms"] for r in g) / [r["ms"] for r in g if r["config"] == DEFAULT][0]
-                 for g in groups.values()]))))}
+    out = {"cases": n,
+           "geomean_pick_over_best": float(np.exp(np.mean(np.log(ratios)))),
+           "within_5pct_of_best": within / max(n, 1),
+           "geomean_gain_over_default": float(np.exp(np.mean(np.log(gains)))),
+           "geomean_best_gain_over_default": float(np.exp(np.mean(np.log(
+               [[r["ms"] for r in g if r["config"] == DEFAULT][0] / min(r["ms"] for r in g)
+                for g in groups.values()]))))}
+    if static is not None:
+        out["static_config"] = static
+        out["geomean_static_gain_over_default"] = float(np.exp(np.mean(np.log(sgains))))
+    return out
+
+
+def main(argv=None):
+    """``sweep FIRST LAST OUT [N_MAX]``: time every configuration on the
+    corpus seeds FIRST..LAST-1 (GPU), appending to OUT.
+    ``compact OUT IN...``: merge sweep files into the compact database."""
+    import argparse
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2205_01598_amd.tune")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s1 = sub.add_parser("sweep")
+    s1.add_argument("first", type=int)
+    s1.add_argument("last", type=int)
+    s1.add_argument("out")
+    s1.add_argument("--n-max", type=float, default=4e6)
+    s2 = sub.add_parser("compact")
+    s2.add_argument("out")
+    s2.add_argument("inputs", nargs="+")
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        sweep(range(a.first, a.last), a.out, n_max=a.n_max, log=lambda m: print(m, flush=True))
+    else:
+        recs = []
+        for f in a.inputs:
+            recs.extend(load_db(f))
+        compact_db(recs, a.out)
+        print(f"{len({(r['seed'], r['p']) for r in recs})} (matrix, p) cases -> {a.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -345,3 +345,53 @@ def test_chebyshev_propagator(baseline):
         h[perm] = a.cpu().numpy()
         assert _rel_err(h, ref) <= 1e-12
     assert abs(np.linalg.norm(h) - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("granularity", ["node", "wavefront"])
+@pytest.mark.parametrize("case", ["c1_many_groups", "27pt_random", "irregular_k4", "bf16"])
+def test_bulk_synchronous_variants(granularity, case):
+    # the launch-per-node and launch-per-wavefront variants run the same chunks
+    # with the same arithmetic as the persistent kernel: equal bit for bit,
+    # and within the FP64 bar of the oracle
+    dev = _dev()
+    k, opts = 1, {}
+    if case == "c1_many_groups":
+        A, p, C = W.stencil_2d(64, 5), 4, 16 * 1024
+        opts = {"tile_nnz": 300}
+    elif case == "27pt_random":
+        A, p, C = W.stencil_27pt_random(20, seed=3)[0], 6, 3 << 20
+        opts = {"root_mode": 1, "tile_nnz": 2000}
+    elif case == "irregular_k4":
+        A, p, C, k = W.zipf_rows(3000, 2.0, seed=5), 5, 1 << 18, 4
+        opts = {"nrhs": 4, "tile_nnz": 200}
+    else:
+        A, p, C = W.stencil_27pt_random(16, seed=4)[0], 4, 1 << 20
+        opts = {"val_dtype": "bf16"}
+    pl = Plan(A, p, C, **opts)
+    assert pl.info()["n_groups"] > 1
+    perm = pl.arrays()[0]
+    x = np.random.default_rng(11).uniform(-1, 1, (A.n, k)) if k > 1 else W.uniform_vector(A.n, seed=11)
+    X = torch.from_numpy(np.ascontiguousarray(_to_plan(x, perm))).to(dev)
+    Y1 = torch.full((p,) + tuple(X.shape), float("nan"), dtype=torch.float64, device=dev)
+    Y2 = torch.full_like(Y1, float("nan"))
+    pl.run(X, Y1)
+    pl.status()
+    pl.run_sync(X, Y2, granularity)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+    if case != "bf16":
+        ref = O.spmv_powers(A, x, p)
+        Y = _unpermute_powers(Y2.cpu().numpy(), perm)
+        check_powers(Y.reshape(ref.shape), ref)
+
+
+def test_bulk_synchronous_rejects_bad_granularity():
+    dev = _dev()
+    A = W.stencil_2d(16, 5)
+    pl = Plan(A, 3, 1 << 16)
+    X = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    Y = torch.zeros((3, A.n), dtype=torch.float64, device=dev)
+    from paper_2205_01598_amd import lib
+    import ctypes
+    st = lib().mpk_run_sync(pl._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), 7, None)
+    assert st == -1

@@ -178,6 +178,33 @@ def test_plan_rgg_and_banded():
     _check_plan(Z, 3, 2 ** 18, 0, tile_nnz=900)
 
 
+def _direct_sum(*blocks):
+    n = sum(b.n for b in blocks)
+    rps, cols, vals, off, base = [np.zeros(1, np.int64)], [], [], 0, 0
+    for b in blocks:
+        rps.append(b.rowptr[1:] + base)
+        cols.append(b.col.astype(np.int64) + off)
+        vals.append(b.val)
+        off += b.n
+        base += b.nnz
+    return W.CSR(n, np.concatenate(rps), np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+
+
+@pytest.mark.parametrize("root_mode", [0, 1])
+def test_plan_large_unsymmetric_components(root_mode):
+    # a non-symmetric pattern (transpose merged in), frontiers of thousands of
+    # vertices (parallel expansion) and several components (restarts at the
+    # smallest unnumbered index), randomly relabelled
+    Z = W.zipf_rows(30000, 1.8, seed=4)
+    S, _ = W.stencil_27pt_random(18, seed=6)
+    iso = W.CSR(50, np.arange(51, dtype=np.int64), np.arange(50, dtype=np.int32), np.ones(50))
+    A = _direct_sum(S, Z, iso)
+    A = W.relabel(A, np.random.default_rng(9).permutation(A.n))
+    pl = _check_plan(A, 4, 2 ** 21, root_mode, tile_nnz=4000)
+    lp = pl.arrays()[1]
+    assert np.diff(lp).max() >= 2048
+
+
 def test_plan_empty_and_single():
     Z = W.CSR(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
     pl = Plan(Z, 3, 1000, upload=False)
