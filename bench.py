@@ -11,7 +11,10 @@ MPK GFLOP/s (2 nnz p / t), speedup over the faster of two tuned baselines
 (p SpMV launches on the matrix as given, and on the BFS-renumbered matrix),
 roofline fraction of the persistent kernel against 8 TB/s HBM on algorithmic
 bytes, mixed-precision (FP32 / BF16 values) throughput and error against the
-FP64 oracle, and the FP64 CPU oracle timed on the host.
+FP64 run, the synchronisation ladder, and the FP64 CPU oracle timed on the
+host (the only use of the oracle here).  Other workloads: 64^2 Laplacian,
+Anderson 128^3 and heat-equation 160^3 Chebyshev propagation, multi-RHS RGG,
+the learned tuner.
 """
 from __future__ import annotations
 
@@ -113,7 +116,9 @@ def bench_small_2d(torch, Plan, W, dev):
 
 
 def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
-    """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8."""
+    """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8.
+    Low-precision errors are measured against the FP64 run of the same
+    steps (whose agreement with the oracle the tests establish)."""
     from paper_2205_01598_amd.cheb import ChebPropagator
 
     A = W.anderson_3d(128, seed=0)
@@ -121,19 +126,10 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
     M, p, r_dt = 32, 8, 10.0
     out = {"workload": "Anderson 128^3 (W=16, open BC, A=H/14), degree 32, p=8, r*dt=10, complex state"}
     ref = None
-    try:
-        import oracle as O
-
-        c = O.cheb_coefficients(M, r_dt)
-        ref = [x]
-        for _ in range(steps_err):
-            ref.append(O.cheb_propagate(A, ref[-1], c))
-    except ImportError:
-        pass
     for dt in ("f64", "f32", "bf16"):
         pl = Plan(A, p, 256 << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=2, tile_nnz=8192)
         perm = pl.arrays()[0].astype(np.int64)
-        prop = ChebPropagator(pl, M, r_dt)
+        prop = ChebPropagator.schroedinger(pl, M, r_dt)
         X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
         acc = torch.empty_like(X)
         tm = timed(torch, lambda: prop.step(X, acc), 20, 3)
@@ -141,19 +137,52 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
         pl.status()
         ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
                "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1)}
-        if ref is not None:
-            errs, state = [], X
-            for s_ in range(steps_err):
-                nxt = torch.empty_like(state)
-                prop.step(state, nxt)
-                h = np.empty((A.n, 2))
-                h[perm] = nxt.cpu().numpy()
-                errs.append(float(f"{np.linalg.norm(h - ref[s_ + 1]) / np.linalg.norm(ref[s_ + 1]):.3e}"))
-                state = nxt
-            ent["rel_err_per_step"] = errs
-            ent["norm_after_steps"] = float(f"{np.linalg.norm(h):.12f}")
+        states, state = [], X
+        for _ in range(steps_err):
+            nxt = torch.empty_like(state)
+            prop.step(state, nxt)
+            h = np.empty((A.n, 2))
+            h[perm] = nxt.cpu().numpy()
+            states.append(h)
+            state = nxt
+        if dt == "f64":
+            ref = states
+        else:
+            ent["rel_err_vs_fp64_per_step"] = [float(f"{np.linalg.norm(a - b) / np.linalg.norm(b):.3e}")
+                                               for a, b in zip(states, ref)]
+        ent["norm_after_steps"] = float(f"{np.linalg.norm(states[-1]):.12f}")
         out[dt] = ent
         del pl, prop
+    return out
+
+
+def bench_heat(torch, Plan, W, dev):
+    """Heat equation on 160^3 with finite differences of order 2, 4, 6
+    (Table 3), degree-32 Chebyshev step (tau = 70, coefficients below 1e-4
+    from degree 32 on) as 4 MPK blocks of p = 8, real coefficients."""
+    from paper_2205_01598_amd.cheb import ChebPropagator, degree_for_cutoff
+
+    M, p, tau = 32, 8, 70.0
+    assert degree_for_cutoff(tau, kind="heat") <= M
+    out = {"workload": "heat equation 160^3, order 2/4/6 finite differences, A = L/r - I, degree 32, p=8, tau=70"}
+    x = W.uniform_vector(160 ** 3, seed=0)
+    for order in (2, 4, 6):
+        A, r = W.heat_operator_3d(160, order)
+        pl = Plan(A, p, 256 << 20, root_mode=1, skew=2, tile_nnz=8192)
+        perm = pl.arrays()[0].astype(np.int64)
+        prop = ChebPropagator.heat(pl, M, tau)
+        X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+        acc = torch.empty_like(X)
+        accb = torch.empty_like(X)
+        tm = timed(torch, lambda: prop.step(X, acc), 10, 2)
+        tb = timed(torch, lambda: prop.step(X, accb, baseline=True), 10, 2)
+        pl.status()
+        diff = float((acc - accb).norm() / accb.norm())
+        out[f"order{order}"] = {"nnz": A.nnz, "step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4),
+                                "speedup": round(tb / tm, 3), "gflops": round(2.0 * A.nnz * M / tm / 1e6, 1),
+                                "mpk_vs_baseline_rel_diff": float(f"{diff:.3e}"),
+                                "norm_ratio": float(f"{float(acc.norm()) / float(X.norm()):.6e}")}
+        del pl, prop, A
     return out
 
 
@@ -229,6 +258,20 @@ def bench_learned_tuner(torch, plan, X, Y, p, log):
     return out
 
 
+def cpu_baseline_leg(A, x, p, flop):
+    """The CPU oracle (plain C, FP64, one host thread) timed on the same
+    input; its output also gives the FP64 error of the GPU result."""
+    import oracle as O
+
+    t0 = time.time()
+    ref = O.spmv_powers(A, x, p)
+    cpu_s = time.time() - t0
+    cpu = {"value": round(flop / cpu_s / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+           "sample": f"one full FP64 p={p} run (p back-to-back CSR SpMVs) of the same 160^3 matrix, "
+                     f"{cpu_s:.1f} s on one host thread"}
+    return cpu, ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +284,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the tuning sweep")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other workloads (2D 64^2, Chebyshev Anderson 128^3, multi-RHS RGG)")
+                    help="skip the other workloads (2D 64^2, Chebyshev Anderson 128^3, multi-RHS RGG, "
+                         "heat 160^3, learned tuner)")
     ap.add_argument("--only-main", action="store_true", help="only the headline p (no p=4/6)")
     ap.add_argument("--probe", action="store_true",
                     help="load-only bandwidth versus footprint (one full pass per launch) and exit")
@@ -353,16 +397,9 @@ def main():
     ref = None
     cpu = None
     if not args.no_cpu:
-        import oracle as O
-
-        t0 = time.time()
-        ref = O.spmv_powers(A, x, p)
-        cpu_s = time.time() - t0
-        cpu = {"value": round(flop / cpu_s / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full FP64 p={p} run (p back-to-back CSR SpMVs) of the same 160^3 matrix, "
-                         f"{cpu_s:.1f} s on one host thread"}
+        cpu, ref = cpu_baseline_leg(A, x, p, flop)
         errs = rel_errs(Yh, ref)
-        log(f"cpu oracle {cpu_s:.1f}s; MPK FP64 max rel err {max(errs):.2e}")
+        log(f"cpu oracle {cpu['sample']}; MPK FP64 max rel err {max(errs):.2e}")
 
     # ---- mixed precision ------------------------------------------------------------
     mixed = {}
@@ -375,10 +412,9 @@ def main():
             tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
             ent = {"ms": round(tm, 4), "gflops": round(flop / tm / 1e6, 1), "baseline_ms": round(tbm, 4),
                    "speedup_vs_fp64_baseline": round(t_base / tm, 3)}
-            if ref is not None:
-                Ym = np.empty((p, n))
-                Ym[:, perm] = Y.cpu().numpy()
-                ent["rel_err_vs_fp64_oracle_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, ref)]
+            Ym = np.empty((p, n))
+            Ym[:, perm] = Y.cpu().numpy()
+            ent["rel_err_vs_fp64_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, Yh)]
             mixed[dt] = ent
             del pm
 
@@ -392,6 +428,8 @@ def main():
         log(f"chebyshev: {extra['chebyshev']}")
         extra["multi_rhs"] = bench_multi_rhs(torch, Plan, W, dev)
         log(f"multi-RHS: {extra['multi_rhs']}")
+        extra["heat"] = bench_heat(torch, Plan, W, dev)
+        log(f"heat: {extra['heat']}")
 
     out = {
         "metric": METRIC,

@@ -127,6 +127,10 @@ typedef struct mpk_plan_info {
  * (coef[2(q-1)] + i coef[2(q-1)+1]) acting on k = 2 columns holding
  * (re, im) of one complex vector.  Coefficient arrays are host memory with p
  * (or 2p) entries, copied into the launch; y_prev and acc are device memory.
+ * With coef0 != NULL (host, 1 value, or 2 = re, im with complex_pairs) the
+ * first power starts the sum instead of adding to it:
+ *     acc = coef0 * y_0 + coef_1 * y_1
+ * so acc need not be initialised (a Chebyshev step's first block).
  * Chebyshev: alpha = (1, 2, 2, ...), beta = 0, gamma = (0, -1, -1, ...) in
  * the first block; later blocks pass the last two vectors of the previous
  * block as y_prev and X and use alpha = 2, gamma = -1 throughout. */
@@ -138,6 +142,7 @@ typedef struct mpk_recurrence {
     int32_t complex_pairs;
     const double *y_prev;
     double *acc;
+    const double *coef0;
 } mpk_recurrence;
 
 typedef struct mpk_plan mpk_plan;

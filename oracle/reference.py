@@ -266,3 +266,32 @@ def cheb_propagate(A, x, coeffs) -> np.ndarray:
         acc += coeffs[k].real * v_next + coeffs[k].imag * np.stack([-v_next[:, 1], v_next[:, 0]], 1)
         v_prev, v = v, v_next
     return acc
+
+def heat_coefficients(M: int, tau: float) -> np.ndarray:
+    """c_k, k = 0..M, of exp(-tau (A + I)) = sum_k c_k T_k(A) (Sec. 7, heat
+    equation with L = r (A + I) and tau = a dt r).
+
+    From the generating function exp(z cos t) = I_0(z) + 2 sum_k I_k(z) cos(k t)
+    at z = -tau, with I_k(-tau) = (-1)^k I_k(tau):
+    c_k = (2 - delta_k0) (-1)^k I_k(tau) exp(-tau).  I_k from scipy.special.iv.
+    """
+    from scipy.special import iv
+
+    k = np.arange(M + 1)
+    return (2.0 - (k == 0)) * ((-1.0) ** k) * iv(k, tau) * np.exp(-tau)
+
+
+def cheb_propagate_real(A, x, coeffs) -> np.ndarray:
+    """One time step x' = sum_k c_k v_k with real coefficients and a real
+    state (n,): v_0 = x, v_1 = A x, v_{k+1} = 2 A v_k - v_{k-1} (Eq. 7-8)."""
+    v_prev = np.asarray(x, dtype=np.float64).copy()
+    acc = coeffs[0] * v_prev
+    if len(coeffs) == 1:
+        return acc
+    v = spmv_powers(A, v_prev, 1)[0]
+    acc = acc + coeffs[1] * v
+    for k in range(2, len(coeffs)):
+        v_next = 2.0 * spmv_powers(A, v, 1)[0] - v_prev
+        acc = acc + coeffs[k] * v_next
+        v_prev, v = v, v_next
+    return acc

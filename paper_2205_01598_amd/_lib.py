@@ -60,7 +60,7 @@ class mpk_recurrence(ctypes.Structure):
     _fields_ = [("alpha", ctypes.POINTER(ctypes.c_double)), ("beta", ctypes.POINTER(ctypes.c_double)),
                 ("gamma", ctypes.POINTER(ctypes.c_double)), ("coef", ctypes.POINTER(ctypes.c_double)),
                 ("complex_pairs", ctypes.c_int32), ("y_prev", ctypes.c_void_p),
-                ("acc", ctypes.c_void_p)]
+                ("acc", ctypes.c_void_p), ("coef0", ctypes.POINTER(ctypes.c_double))]
 
 
 _P = ctypes.c_void_p

@@ -55,6 +55,8 @@ struct RecArgs {
     const double *y_prev;  // y_{-1}
     double *acc;           // accumulator or null
     int32_t complex_pairs;
+    int32_t start_acc;     // power 1 sets acc = c0 * y_0 + coef_1 * y_1
+    double c0_re, c0_im;
 };
 
 // Output store.  COH = true (inside the persistent MPK kernel, where other
@@ -107,15 +109,27 @@ __device__ __forceinline__ void store_row(int64_t r, const double *v_in, const d
     for (int c = 0; c < K; ++c) put<COH>(y + r * K + c, v[c]);
     if constexpr (REC) {
         if (rec.acc) {
+            // the running sum: acc, or c0 * y_0 when power 1 starts it (x is y_0 then)
+            const bool start = rec.start_acc && q == 1;
             if (K == 2 && rec.complex_pairs) {
                 const double cr = rec.coef_re[q - 1], ci = rec.coef_im[q - 1];
-                const double a0 = rec.acc[r * K + 0], a1 = rec.acc[r * K + 1];
+                double a0, a1;
+                if (start) {
+                    const double x0 = x[r * K + 0], x1 = x[r * K + 1];
+                    a0 = rec.c0_re * x0 - rec.c0_im * x1;
+                    a1 = rec.c0_re * x1 + rec.c0_im * x0;
+                } else {
+                    a0 = rec.acc[r * K + 0];
+                    a1 = rec.acc[r * K + 1];
+                }
                 put<COH>(rec.acc + r * K + 0, a0 + (cr * v[0] - ci * v[1]));
                 put<COH>(rec.acc + r * K + 1, a1 + (cr * v[1] + ci * v[0]));
             } else {
 #pragma unroll
-                for (int c = 0; c < K; ++c)
-                    put<COH>(rec.acc + r * K + c, rec.acc[r * K + c] + rec.coef_re[q - 1] * v[c]);
+                for (int c = 0; c < K; ++c) {
+                    const double a = start ? rec.c0_re * x[r * K + c] : rec.acc[r * K + c];
+                    put<COH>(rec.acc + r * K + c, a + rec.coef_re[q - 1] * v[c]);
+                }
             }
         }
     }

@@ -460,9 +460,15 @@ mpk_status fill_rec(const mpk_recurrence *r, int p, int K, RecArgs &out) {
             return fail(MPK_ERR_ARG, "gamma[0] != 0 needs y_prev");
     }
     if (r->acc && !r->coef) return fail(MPK_ERR_ARG, "acc needs coef");
+    if (r->coef0 && !r->acc) return fail(MPK_ERR_ARG, "coef0 needs acc");
     out.y_prev = r->y_prev;
     out.acc = r->acc;
     out.complex_pairs = r->complex_pairs;
+    if (r->coef0) {
+        out.start_acc = 1;
+        out.c0_re = r->coef0[0];
+        out.c0_im = r->complex_pairs ? r->coef0[1] : 0.0;
+    }
     return MPK_OK;
 }
 

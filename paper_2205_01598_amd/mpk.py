@@ -45,7 +45,7 @@ class Recurrence:
     """Three-term recurrence epilogue (see ``mpk_recurrence`` in include/mpk.h)."""
 
     def __init__(self, alpha, beta=None, gamma=None, coef=None, complex_pairs=False,
-                 y_prev=None, acc=None):
+                 y_prev=None, acc=None, coef0=None):
         p = len(alpha)
         self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
         self.beta = np.ascontiguousarray(beta if beta is not None else np.zeros(p), dtype=np.float64)
@@ -54,6 +54,7 @@ class Recurrence:
         self.complex_pairs = bool(complex_pairs)
         self.y_prev = y_prev
         self.acc = acc
+        self.coef0 = None if coef0 is None else np.ascontiguousarray(np.atleast_1d(coef0), dtype=np.float64)
 
     def struct(self):
         return _lib.mpk_recurrence(
@@ -61,7 +62,8 @@ class Recurrence:
             _f64p(self.coef) if self.coef is not None else None,
             int(self.complex_pairs),
             int(self.y_prev.data_ptr()) if self.y_prev is not None else None,
-            int(self.acc.data_ptr()) if self.acc is not None else None)
+            int(self.acc.data_ptr()) if self.acc is not None else None,
+            _f64p(self.coef0) if self.coef0 is not None else None)
 
 
 class Plan:

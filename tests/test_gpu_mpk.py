@@ -332,7 +332,7 @@ def test_chebyshev_propagator(baseline):
     ref2 = O.cheb_propagate(A, ref1, c)
     pl = Plan(A, p, 1 << 20, nrhs=2, root_mode=1, tile_nnz=700, skew=2)
     perm = pl.arrays()[0].astype(np.int64)
-    prop = ChebPropagator(pl, M, r_dt)
+    prop = ChebPropagator.schroedinger(pl, M, r_dt)
     assert np.allclose(prop.c, c, rtol=0, atol=1e-15)
     X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
     a1 = torch.empty_like(X)
@@ -395,3 +395,34 @@ def test_bulk_synchronous_rejects_bad_granularity():
     import ctypes
     st = lib().mpk_run_sync(pl._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), 7, None)
     assert st == -1
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("baseline", [False, True])
+def test_heat_propagator(order, baseline):
+    # heat equation with real modified-Bessel coefficients; the accumulator is
+    # NaN-poisoned: the first power must start the sum (coef0), not add to it
+    from paper_2205_01598_amd.cheb import ChebPropagator, heat_coefficients
+
+    dev = _dev()
+    A, r = W.heat_operator_3d(12, order)
+    x = W.uniform_vector(A.n, seed=order)
+    M, p, tau = 16, 8, 9.0
+    c = O.heat_coefficients(M, tau)
+    assert np.allclose(heat_coefficients(M, tau), c, rtol=1e-13, atol=1e-16)
+    ref1 = O.cheb_propagate_real(A, x, c)
+    ref2 = O.cheb_propagate_real(A, ref1, c)
+    pl = Plan(A, p, 1 << 18, root_mode=1, tile_nnz=900, skew=2)
+    assert pl.info()["n_groups"] > 1
+    perm = pl.arrays()[0].astype(np.int64)
+    prop = ChebPropagator.heat(pl, M, tau)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    a1 = torch.full_like(X, float("nan"))
+    a2 = torch.full_like(X, float("nan"))
+    prop.step(X, a1, baseline=baseline)
+    prop.step(a1, a2, baseline=baseline)
+    pl.status()
+    for a, ref in ((a1, ref1), (a2, ref2)):
+        h = np.empty(A.n)
+        h[perm] = a.cpu().numpy()
+        assert _rel_err(h, ref) <= 1e-12

@@ -431,3 +431,60 @@ def test_rgg_shape():
     assert 13.0 < deg.mean() < 17.0
     M = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
     assert (M != M.T).nnz == 0
+
+
+# ----------------------------------------------------------------------------
+# heat-equation Chebyshev propagation (Sec. 7, real modified-Bessel coefficients)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.5, 5.0, 20.0, 70.0])
+def test_heat_coefficients_generating_function(tau):
+    # sum_k c_k T_k(x) = exp(-tau (x + 1)) on [-1, 1]; T_k(cos t) = cos(k t)
+    c = O.heat_coefficients(120, tau)
+    t = np.linspace(0.0, np.pi, 41)
+    series = np.cos(np.outer(t, np.arange(121))) @ c
+    assert np.allclose(series, np.exp(-tau * (np.cos(t) + 1.0)), rtol=1e-10, atol=1e-14)
+
+
+def test_heat_coefficients_sign_pattern():
+    # a dropped (-1)^k would expand exp(+tau x) instead: at x = -1 the two
+    # differ by exp(2 tau)
+    tau = 3.0
+    c = O.heat_coefficients(60, tau)
+    assert np.all(c[1::2] < 0) and np.all(c[0::2] > 0)
+    assert abs(np.sum(c * (-1.0) ** np.arange(61)) - 1.0) < 1e-12  # x = -1: exp(0)
+
+
+def test_heat_operator_spectrum_and_eigenvectors():
+    # order 2: L = -Laplacian_h has the Dirichlet eigenvectors
+    # v = prod_d sin(j_d pi (x_d + 1) / (n + 1)), eigenvalue
+    # sum_d (2 - 2 cos(j_d pi / (n + 1))); A = L / 6 - I, so one step with
+    # tau gives exp(-tau lambda / 6) v
+    n = 7
+    A, r = W.heat_operator_3d(n, 2)
+    assert r == 6.0
+    g = np.arange(n)
+    for j in [(1, 1, 1), (2, 5, 3), (7, 7, 7)]:
+        s = [np.sin(jd * np.pi * (g + 1) / (n + 1)) for jd in j]
+        v = np.einsum("i,j,k->kji", s[0], s[1], s[2]).reshape(-1)  # x fastest
+        lam = sum(2.0 - 2.0 * np.cos(jd * np.pi / (n + 1)) for jd in j)
+        tau = 10.0
+        out = O.cheb_propagate_real(A, v, O.heat_coefficients(40, tau))
+        assert np.allclose(out, np.exp(-tau * lam / 6.0) * v, rtol=0, atol=1e-12 * np.abs(v).max())
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_heat_propagate_vs_expm(order):
+    from scipy.linalg import expm
+
+    A, r = W.heat_operator_3d(5, order)
+    D = A.to_dense()
+    ev = np.linalg.eigvalsh(D)
+    assert ev.min() >= -1.0 - 1e-12 and ev.max() <= 1.0 + 1e-12
+    x = W.uniform_vector(A.n, seed=4)
+    tau = 12.0
+    ref = expm(-tau * (D + np.eye(A.n))) @ x
+    out = O.cheb_propagate_real(A, x, O.heat_coefficients(48, tau))
+    assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref) + 1e-15
+    # heat flow contracts the state
+    assert np.linalg.norm(out) < np.linalg.norm(x)

@@ -10,6 +10,7 @@ from .matrices import (  # noqa: F401
     stencil_2d,
     stencil_3d,
     star_stencil_3d,
+    heat_operator_3d,
     stencil_27pt_random,
     anderson_3d,
     random_geometric,

@@ -205,6 +205,26 @@ def star_stencil_3d(n: int, order: int) -> CSR:
     return _compress(cols, vals, valid)
 
 
+def heat_operator_3d(n: int, order: int):
+    """Heat-equation operator of Table 3 scaled for a Chebyshev expansion.
+
+    L = -(finite-difference Laplacian of spatial order 2, 4 or 6 on an n^3
+    grid, zero outside) is symmetric positive semidefinite with spectrum in
+    [0, 2r], r = half the largest Gershgorin row sum of an interior row (12,
+    16 and 163/9 for the three orders).  Returns (A, r) with the stored
+    matrix A = L / r - I, whose spectrum lies in [-1, 1].
+    """
+    S = star_stencil_3d(n, order)
+    weights = {2: [-2.0, 1.0],
+               4: [-5.0 / 2, 4.0 / 3, -1.0 / 12],
+               6: [-49.0 / 18, 3.0 / 2, -3.0 / 20, 1.0 / 90]}[order]
+    gersh = 3.0 * (abs(weights[0]) + 2.0 * sum(abs(w) for w in weights[1:]))
+    r = gersh / 2.0
+    rows = np.repeat(np.arange(S.n), np.diff(S.rowptr))
+    val = -S.val / r - (S.col.astype(np.int64) == rows)
+    return CSR(S.n, S.rowptr.copy(), S.col.copy(), val), r
+
+
 def stencil_27pt_random(n: int, seed: int = 0, permute: bool = True):
     """27-point stencil on an n^3 grid with random values and a dominant diagonal.
 
