@@ -316,6 +316,15 @@ def main():
     plan_s = time.time() - t0
     perm = plan.arrays()[0].astype(np.int64)
     log(f"plan: {plan.info()['n_levels']} levels in {plan_s:.1f}s")
+    # the same plan with the breadth-first levels on the GPU
+    t0 = time.time()
+    pdev = Plan(A, p, 256 << 20, root_mode=1, upload=False, levels_on_device=1)
+    plan_dev_s = time.time() - t0
+    assert np.array_equal(pdev.arrays()[0], plan.arrays()[0])
+    plan_phases = {"host_levels": [round(v, 3) for v in plan.info()["phase_seconds"]],
+                   "device_levels": [round(v, 3) for v in pdev.info()["phase_seconds"]]}
+    del pdev
+    log(f"plan with device levels: {plan_dev_s:.2f}s, phases {plan_phases}")
     X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
     X0 = torch.from_numpy(x).to(dev)
     Y = torch.empty((p, n), dtype=torch.float64, device=dev)
@@ -454,6 +463,8 @@ def main():
         "baseline_gflops": round(flop / t_base / 1e6, 1),
         "plan_seconds": round(plan_s, 2),
         "plan_spmv_equivalents": round(plan_s / (t_base / p * 1e-3), 0),
+        "plan_seconds_levels_on_device": round(plan_dev_s, 2),
+        "plan_phase_seconds": plan_phases,
         "sync_ladder": ladder,
         "other_powers": other,
         "mixed_precision": mixed,

@@ -93,6 +93,12 @@ int32_t chunk_nnz_host(int32_t k);
 // rows per chunk cap: bounds the chunk's row-pointer slice kept in LDS
 constexpr int32_t kChunkRows = 1024;
 
+// Breadth-first levels and root on the current GPU (levels_device.hip): the
+// same root, permutation and level pointers as the host planner, from the
+// undirected graph (ptr[n+1], adj[ptr[n]], lists ascending, no diagonal).
+mpk_status device_bfs_levels(int64_t n, const int64_t *ptr, const int32_t *adj, int32_t root_mode, int64_t *root_out,
+                             std::vector<int32_t> &perm, std::vector<int32_t> &level_ptr);
+
 // Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
 int32_t bytes_per_nnz(int32_t dtype);
 

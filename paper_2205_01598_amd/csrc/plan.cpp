@@ -621,6 +621,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.reserved0 != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+    if (opt.levels_on_device != 0 && opt.levels_on_device != 1) return fail(MPK_ERR_ARG, "levels_on_device must be 0 or 1");
 
     const int64_t n = A->n;
     hp.n = n;
@@ -638,8 +639,13 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
         build_graph(A, g);
         auto tb = now();
         hp.root = 0;
-        if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
-        bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+        if (opt.levels_on_device) {
+            st = device_bfs_levels(n, g.ptr.data(), g.adj.data(), opt.root_mode, &hp.root, hp.perm, hp.level_ptr);
+            if (st != MPK_OK) return st;
+        } else {
+            if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
+            bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+        }
         hp.phase_seconds[0] = secs(ta, tb);
         hp.phase_seconds[1] = secs(tb, now());
         { Graph().adj.swap(g.adj); }
