@@ -94,7 +94,9 @@ typedef struct mpk_options {
                                  on MI355X), so a tile meets the same L2 at every power */
     int32_t levels_on_device; /* 1: breadth-first levels and root search of mpk_plan_create run on the
                                  current GPU (same result as the host, bit for bit); 0 (default): host */
-    int32_t reserved[4];
+    int32_t force_acquire;    /* 1: every dependency wait ends with an agent-scope acquire fence even
+                                 when mpk_run could do without it (see mpk_plan_info.line_closed_deps) */
+    int32_t reserved[3];
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */
@@ -117,6 +119,14 @@ typedef struct mpk_plan_info {
     double plan_seconds;      /* host time spent in mpk_plan_create */
     double phase_seconds[4];  /* of which: graph of A + A^T, root search + BFS, renumbering,
                                  groups/schedule/tiles */
+    int32_t line_closed_deps; /* 1: mpk_run can skip the acquire fence after each dependency wait.
+                                 The planner widened every dependency range to whole 128-byte lines
+                                 of a vector slice and every widened dependency is an earlier
+                                 ticket; mpk_run then skips the fence when Y is 128-byte aligned,
+                                 N*k*8 is a multiple of 128 and force_acquire is 0.  No line of a
+                                 power is read before all its rows are final, so no cache holds a
+                                 stale copy; the accumulator is read with agent-scope loads. */
+    int32_t last_run_fenced;  /* the last mpk_run used the acquire fence: 1, did not: 0, no run: -1 */
 } mpk_plan_info;
 
 /* Three-term recurrence epilogue for mpk_run / mpk_run_baseline (Sec. 7,
@@ -205,8 +215,11 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
  * (lo, hi) tile ranges, inclusive, in level groups g-1, g and g+1 of the
  * tile's group g (lo > hi: no dependency there).  Before computing power q a
  * tile waits for power q-1 of exactly these tiles (Sec. 4.3, with Eq. (4)
- * limiting the reads of a group to its two neighbour groups). */
-mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges);
+ * limiting the reads of a group to its two neighbour groups).
+ * line_closed = 1 returns the same ranges widened to whole 128-byte lines of
+ * a vector slice (they may reach one tile into groups g-2 and g+2), which
+ * mpk_run uses when it skips the acquire fence. */
+mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges, int32_t line_closed);
 
 /* Matrix and level features for the learned tuner, host, MPK_NUM_FEATURES
  * doubles: log10 N, log10 nnz, mean / standard deviation / log2(max+1) of the

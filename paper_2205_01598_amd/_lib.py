@@ -42,7 +42,8 @@ class mpk_options(ctypes.Structure):
                 ("tile_nnz", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
                 ("skew", ctypes.c_int32), ("xcd_streams", ctypes.c_int32),
-                ("levels_on_device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("levels_on_device", ctypes.c_int32), ("force_acquire", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class mpk_plan_info(ctypes.Structure):
@@ -53,7 +54,8 @@ class mpk_plan_info(ctypes.Structure):
                 ("violating_groups", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
                 ("workgroups", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("tile_nnz", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
-                ("plan_seconds", ctypes.c_double), ("phase_seconds", ctypes.c_double * 4)]
+                ("plan_seconds", ctypes.c_double), ("phase_seconds", ctypes.c_double * 4),
+                ("line_closed_deps", ctypes.c_int32), ("last_run_fenced", ctypes.c_int32)]
 
 
 class mpk_recurrence(ctypes.Structure):
@@ -78,7 +80,7 @@ SIGNATURES = {
     "mpk_plan_arrays": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
     "mpk_plan_matrix": (ctypes.c_int32, [_P, _I64P, _I32P, _F64P]),
     "mpk_plan_tiles": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
-    "mpk_plan_tile_deps": (ctypes.c_int32, [_P, _I32P]),
+    "mpk_plan_tile_deps": (ctypes.c_int32, [_P, _I32P, ctypes.c_int32]),
     "mpk_plan_features": (ctypes.c_int32, [_P, _F64P]),
     "mpk_plan_upload": (ctypes.c_int32, [_P]),
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),

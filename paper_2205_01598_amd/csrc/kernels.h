@@ -64,6 +64,17 @@ struct RecArgs {
 // agent-scope relaxed atomic store, which is written through to the
 // device-coherent level, so the publishing workgroup only has to wait for its
 // stores to complete instead of writing back its whole L2.
+// Read of a value other workgroups update in the same launch (the running
+// sum of the recurrence): an agent-scope atomic load, coherent whatever the
+// caches hold.
+template <bool COH>
+__device__ __forceinline__ double get(const double *p) {
+    if constexpr (COH)
+        return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
 template <bool COH>
 __device__ __forceinline__ void put(double *p, double v) {
     if constexpr (COH)
@@ -119,15 +130,15 @@ __device__ __forceinline__ void store_row(int64_t r, const double *v_in, const d
                     a0 = rec.c0_re * x0 - rec.c0_im * x1;
                     a1 = rec.c0_re * x1 + rec.c0_im * x0;
                 } else {
-                    a0 = rec.acc[r * K + 0];
-                    a1 = rec.acc[r * K + 1];
+                    a0 = get<COH>(rec.acc + r * K + 0);
+                    a1 = get<COH>(rec.acc + r * K + 1);
                 }
                 put<COH>(rec.acc + r * K + 0, a0 + (cr * v[0] - ci * v[1]));
                 put<COH>(rec.acc + r * K + 1, a1 + (cr * v[1] + ci * v[0]));
             } else {
 #pragma unroll
                 for (int c = 0; c < K; ++c) {
-                    const double a = start ? rec.c0_re * x[r * K + c] : rec.acc[r * K + c];
+                    const double a = start ? rec.c0_re * x[r * K + c] : get<COH>(rec.acc + r * K + c);
                     put<COH>(rec.acc + r * K + c, a + rec.coef_re[q - 1] * v[c]);
                 }
             }

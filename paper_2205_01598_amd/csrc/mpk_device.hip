@@ -46,12 +46,14 @@ struct mpk_plan {
     int32_t workgroups = 0;
     int32_t num_cus = 0;
     uint32_t epoch = 0;
+    int32_t last_run_fenced = -1;
     uint64_t device_bytes = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr;
     void *d_val = nullptr;
     int32_t *d_tile_row = nullptr, *d_work = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_chunk = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;  // d_chunk: int4 per chunk
+    int32_t *d_dep3x = nullptr;
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
     std::vector<void *> allocs;
 };
@@ -218,6 +220,7 @@ struct MpkArgs {
     int32_t nstreams;
     int32_t stream_ptr[kMaxStreams + 1];
     int64_t watchdog;
+    int32_t acquire;  // 1: agent-scope acquire fence after every dependency wait
 };
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
@@ -255,7 +258,9 @@ __device__ bool wait_flags(const uint32_t *f, const int32_t *d, const MpkArgs &a
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // Without line-closed dependencies a cache may hold a line of y_{q-1}
+    // read before all its rows were final: invalidate before reading.
+    if (a.acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -588,6 +593,8 @@ mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info) {
     info->val_dtype = h.opt.val_dtype;
     info->plan_seconds = h.plan_seconds;
     for (int i = 0; i < 4; ++i) info->phase_seconds[i] = h.phase_seconds[i];
+    info->line_closed_deps = h.line_closed_ok ? 1 : 0;
+    info->last_run_fenced = plan->last_run_fenced;
     return MPK_OK;
 }
 
@@ -623,9 +630,10 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
     return MPK_OK;
 }
 
-mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges) {
+mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges, int32_t line_closed) {
     if (!plan) return fail(MPK_ERR_ARG, "null plan");
-    if (ranges) std::copy(plan->hp.dep3.begin(), plan->hp.dep3.end(), ranges);
+    const std::vector<int32_t> &d = line_closed ? plan->hp.dep3x : plan->hp.dep3;
+    if (ranges) std::copy(d.begin(), d.end(), ranges);
     return MPK_OK;
 }
 
@@ -662,6 +670,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     plan->d_val = dv;
     if ((e = dev_alloc(al, &plan->d_tile_row, T + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "tiles");
     if ((e = dev_alloc(al, &plan->d_dep3, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_dep3x, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_work, W, &bytes)) != hipSuccess) return cleanup_fail(e, "work");
     if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
     if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
@@ -677,6 +686,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_val, vbuf.data(), h.nnz * value_bytes(h.opt.val_dtype)},
         {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
         {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
+        {plan->d_dep3x, h.dep3x.data(), sizeof(int32_t) * 6 * T},
         {plan->d_work, h.work_streams.data(), sizeof(int32_t) * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
         {plan->d_chunk, desc.data(), sizeof(int32_t) * desc.size()},
@@ -756,7 +766,13 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.col = plan->d_col;
     a.val = plan->d_val;
     a.tile_row = plan->d_tile_row;
-    a.dep3 = plan->d_dep3;
+    // skip the acquire fence when every line of a power slice belongs to
+    // tiles the reader waits for (line-closed ranges, aligned slices)
+    const bool closed = h.line_closed_ok && !h.opt.force_acquire && (reinterpret_cast<uintptr_t>(Y) % 128) == 0 &&
+                        ((h.n * h.opt.nrhs * 8) % 128) == 0;
+    a.acquire = closed ? 0 : 1;
+    plan->last_run_fenced = a.acquire;
+    a.dep3 = closed ? plan->d_dep3x : plan->d_dep3;
     a.work = plan->d_work;
     a.n = (int32_t)h.n;
     a.ntiles = (int32_t)h.dep_lo.size();

@@ -39,6 +39,8 @@ struct HostPlan {
     std::vector<int32_t> tile_group; // n_tiles
     std::vector<int32_t> dep_lo, dep_hi;  // n_tiles: all tiles a tile waits for
     std::vector<int32_t> dep3;       // 6*n_tiles: (lo, hi) in groups g-1, g, g+1 (lo > hi: none)
+    std::vector<int32_t> dep3x;      // the same ranges widened to whole cache lines
+    bool line_closed_ok = false;     // every widened dependency is an earlier ticket
     std::vector<int32_t> group_tile; // G+1
     std::vector<int32_t> work;       // tickets: tile*64 + (q-1)
     std::vector<int32_t> stream_ptr; // xcd_streams+1: ticket streams, each in `work` order
@@ -57,7 +59,8 @@ struct ScheduleState {
     int32_t p;
     uint64_t cache_bytes;
     mpk_options opt;
-    std::vector<int32_t> group_ptr, schedule, tile_row, tile_group, dep_lo, dep_hi, dep3, group_tile, work,
+    bool line_closed_ok;
+    std::vector<int32_t> group_ptr, schedule, tile_row, tile_group, dep_lo, dep_hi, dep3, dep3x, group_tile, work,
         stream_ptr, work_streams, chunk_row, tile_chunk;
     int64_t max_group_nnz, violating_groups;
     int32_t tile_nnz;

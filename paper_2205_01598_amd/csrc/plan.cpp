@@ -479,6 +479,37 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         }
         if (bad) return fail(MPK_ERR_CSR, "internal: tile dependency crosses more than one level group");
 
+        // Line-closed ranges, for runs without the acquire fence: every range
+        // widened to whole 128-byte lines of an N x k FP64 vector slice whose
+        // rows start on a line boundary (R rows per line), so a tile also
+        // waits for every tile that shares a cache line with a row it reads or
+        // writes; no line is then read before all its rows are final.  Valid
+        // only if every widened dependency (u, q-1) is still an earlier ticket
+        // than (t, q): group(u) <= g + skew.
+        {
+            const int64_t Rl = std::max<int64_t>(1, 128 / (8 * (int64_t)opt.nrhs));
+            hp.dep3x.assign(6 * T, 0);
+            bool closed_ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : closed_ok)
+            for (int64_t t = 0; t < T; ++t) {
+                for (int m = 0; m < 3; ++m) {
+                    const int32_t lo = hp.dep3[6 * t + 2 * m], hi = hp.dep3[6 * t + 2 * m + 1];
+                    if (lo > hi) {
+                        hp.dep3x[6 * t + 2 * m] = lo;
+                        hp.dep3x[6 * t + 2 * m + 1] = hi;
+                        continue;
+                    }
+                    const int64_t f = hp.tile_row[lo], l = hp.tile_row[hi + 1] - 1;
+                    const int64_t f2 = f - f % Rl, l2 = std::min<int64_t>(n - 1, l + (Rl - 1 - l % Rl));
+                    const int64_t lo2 = tile_of(f2), hi2 = tile_of(l2);
+                    hp.dep3x[6 * t + 2 * m] = (int32_t)lo2;
+                    hp.dep3x[6 * t + 2 * m + 1] = (int32_t)hi2;
+                    closed_ok = closed_ok && hp.tile_group[hi2] <= hp.tile_group[t] + opt.skew;
+                }
+            }
+            hp.line_closed_ok = closed_ok;
+        }
+
         // kernel chunks inside every tile
         hp.chunk_row.clear();
         hp.tile_chunk.assign(T + 1, 0);
@@ -545,6 +576,8 @@ void save_schedule(HostPlan &hp, ScheduleState &s) {
     s.dep_lo = hp.dep_lo;
     s.dep_hi = hp.dep_hi;
     s.dep3 = hp.dep3;
+    s.dep3x = hp.dep3x;
+    s.line_closed_ok = hp.line_closed_ok;
     s.group_tile = hp.group_tile;
     s.work = hp.work;
     s.stream_ptr = hp.stream_ptr;
@@ -567,6 +600,8 @@ void restore_schedule(HostPlan &hp, ScheduleState &s) {
     hp.dep_lo.swap(s.dep_lo);
     hp.dep_hi.swap(s.dep_hi);
     hp.dep3.swap(s.dep3);
+    hp.dep3x.swap(s.dep3x);
+    hp.line_closed_ok = s.line_closed_ok;
     hp.group_tile.swap(s.group_tile);
     hp.work.swap(s.work);
     hp.stream_ptr.swap(s.stream_ptr);
@@ -622,6 +657,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
     if (opt.levels_on_device != 0 && opt.levels_on_device != 1) return fail(MPK_ERR_ARG, "levels_on_device must be 0 or 1");
+    if (opt.force_acquire != 0 && opt.force_acquire != 1) return fail(MPK_ERR_ARG, "force_acquire must be 0 or 1");
 
     const int64_t n = A->n;
     hp.n = n;

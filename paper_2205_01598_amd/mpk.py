@@ -140,10 +140,10 @@ class Plan:
                                    hi.ctypes.data_as(P), work.ctypes.data_as(P)))
         return tr, lo, hi, work
 
-    def tile_deps(self):
+    def tile_deps(self, line_closed: bool = False):
         T = self.info()["n_tiles"]
         d = np.empty(6 * T, np.int32)
-        check(lib().mpk_plan_tile_deps(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        check(lib().mpk_plan_tile_deps(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(line_closed)))
         return d.reshape(T, 6)
 
     # -- device calls ------------------------------------------------------------

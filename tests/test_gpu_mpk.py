@@ -426,3 +426,61 @@ def test_heat_propagator(order, baseline):
         h = np.empty(A.n)
         h[perm] = a.cpu().numpy()
         assert _rel_err(h, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["27pt_k1", "zipf_k4", "27pt_k2_rec", "misaligned_y"])
+def test_line_closed_runs_without_fence(case):
+    # with line-closed dependency ranges mpk_run skips the acquire fence; the
+    # results must equal the fenced run bit for bit and meet the oracle bar.
+    # A Y that is not 128-byte aligned makes the run fall back to the fence.
+    dev = _dev()
+    k = {"27pt_k1": 1, "zipf_k4": 4, "27pt_k2_rec": 2, "misaligned_y": 1}[case]
+    if case == "zipf_k4":
+        A = W.zipf_rows(8192, 2.0, seed=7)
+    else:
+        A = W.stencil_27pt_random(32, seed=5)[0]
+    p = 6
+    opts = dict(root_mode=1, skew=2, tile_nnz=1200, nrhs=k)
+    pl = Plan(A, p, 2 << 20, **opts)
+    pf = Plan(A, p, 2 << 20, force_acquire=1, **opts)
+    assert pl.info()["line_closed_deps"] == 1 and pl.info()["n_groups"] > 2
+    perm = pl.arrays()[0].astype(np.int64)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (A.n, k)) if k > 1 else rng.uniform(-1, 1, A.n)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    shape = (p,) + tuple(X.shape)
+    if case == "misaligned_y":
+        raw = torch.full((int(np.prod(shape)) + 1,), float("nan"), dtype=torch.float64, device=dev)
+        Y1 = raw[1:].view(shape)
+    else:
+        Y1 = torch.full(shape, float("nan"), dtype=torch.float64, device=dev)
+    Y2 = torch.full(shape, float("nan"), dtype=torch.float64, device=dev)
+    if case == "27pt_k2_rec":
+        alpha = np.array([1.0] + [2.0] * (p - 1))
+        gamma = np.array([0.0] + [-1.0] * (p - 1))
+        coef = rng.uniform(-1, 1, 2 * p)
+        acc1 = torch.full_like(X, float("nan"))
+        acc2 = torch.full_like(X, float("nan"))
+        c0 = np.array([0.3, -0.2])
+        pl.run(X, Y1, Recurrence(alpha, None, gamma, coef, True, None, acc1, coef0=c0))
+        pf.run(X, Y2, Recurrence(alpha, None, gamma, coef, True, None, acc2, coef0=c0))
+    else:
+        pl.run(X, Y1)
+        pf.run(X, Y2)
+    pl.status()
+    pf.status()
+    assert pl.info()["last_run_fenced"] == (1 if case == "misaligned_y" else 0)
+    assert pf.info()["last_run_fenced"] == 1
+    assert torch.equal(Y1, Y2)
+    if case == "27pt_k2_rec":
+        assert torch.equal(acc1, acc2)
+    else:
+        ref = O.spmv_powers(A, x, p)
+        check_powers(_unpermute_powers(Y1.cpu().numpy(), perm).reshape(ref.shape), ref)
+    if case != "27pt_k2_rec":
+        # repeated runs reuse the epoch-stamped flags and give the same bits
+        for _ in range(3):
+            Y1.fill_(float("nan"))
+            pl.run(X, Y1)
+            pl.status()
+            assert torch.equal(Y1, Y2)

@@ -38,11 +38,11 @@ def _check_plan(A, p, C, root_mode=0, f=0.5, dtype="f64", **kw):
     rp, col, val = pl.matrix()
     orp, ocol, oval = O.permute_symmetric(A, operm)
     assert np.array_equal(rp, orp) and np.array_equal(col, ocol) and np.array_equal(val, oval)
-    _check_tiles(pl, lp, gp, rp, col)
+    _check_tiles(pl, lp, gp, rp, col, skew=kw.get("skew", 1))
     return pl
 
 
-def _check_tiles(pl, lp, gp, rp, col):
+def _check_tiles(pl, lp, gp, rp, col, skew=1):
     tr, lo, hi, work = pl.tiles()
     inf = pl.info()
     T = inf["n_tiles"]
@@ -83,6 +83,27 @@ def _check_tiles(pl, lp, gp, rp, col):
             assert ctile[sel].min() == a and ctile[sel].max() == b
             covered |= (ctile >= a) & (ctile <= b)
         assert covered.all()
+    # line-closed ranges: contain the tight ones, cover every row that shares
+    # a 128-byte line of an aligned N x k slice with a row of the tight
+    # range, and stop at the first tile beyond; the plan flag says whether
+    # all of them are earlier tickets
+    k = inf["nrhs"]
+    R = max(1, 128 // (8 * k))
+    dx = pl.tile_deps(line_closed=True)
+    order_ok = True
+    for t in range(T):
+        for m in range(3):
+            a, b = d3[t, 2 * m], d3[t, 2 * m + 1]
+            ax, bx = dx[t, 2 * m], dx[t, 2 * m + 1]
+            if a > b:
+                assert (ax, bx) == (a, b)
+                continue
+            f, l = tr[a], tr[b + 1] - 1
+            f2, l2 = f - f % R, min(n - 1, l + (R - 1 - l % R))
+            assert ax <= a and bx >= b
+            assert tr[ax] <= f2 < tr[ax + 1] and tr[bx] <= l2 < tr[bx + 1]
+            order_ok &= bool(tile_group[bx] <= tile_group[t] + skew)
+    assert inf["line_closed_deps"] == int(order_ok)
     # tickets: every (tile, power) once, in Lp diagonal order of the groups,
     # and every dependency is an earlier ticket
     tile = work // 64
