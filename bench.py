@@ -340,8 +340,8 @@ def main():
     log(f"baselines (ms): {base}")
 
     # ---- MPK configuration: small sweep on the same levels ------------------------
-    cands = [dict(skew=2, cache=256, tile=4096), dict(skew=2, cache=1024, tile=16384),
-             dict(skew=2, cache=512, tile=8192), dict(skew=1, cache=1024, tile=8192)]
+    cands = [dict(skew=2, cache=256, tile=8192), dict(skew=2, cache=256, tile=6144),
+             dict(skew=2, cache=256, tile=4096), dict(skew=2, cache=512, tile=8192)]
     if args.quick:
         cands = cands[:1]
     best = None

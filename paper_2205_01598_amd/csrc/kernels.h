@@ -146,6 +146,117 @@ __device__ __forceinline__ void store_row(int64_t r, const double *v_in, const d
     }
 }
 
+// Registers of one chunk between its matrix loads and its gathers.
+template <typename VT, int K>
+struct ChunkRegs {
+    static constexpr int NRB = (kChunkRows + 1 + kBlock - 1) / kBlock;
+    int cj[kProdPerThread];
+    typename AccumType<VT>::T a[kProdPerThread];
+    int rbv[NRB];
+};
+
+// A chunk of the common kind: at least one and at most chunk_nnz(K) stored
+// nonzeros (uniform test).
+template <int K>
+__device__ __forceinline__ bool plain_chunk(const int4 d) {
+    return d.w > d.z && d.w - d.z <= chunk_nnz(K);
+}
+
+// Phase 1, first half, of a plain chunk d = (r0, r1, j0, j1): the row
+// pointers rowptr[r0 .. r1] (uniform guards) and the chunk's col/val entries.
+// Every load is unconditional (slots past the chunk re-read its last entry,
+// whose product phase 2 never reads), so they are all in flight together.
+// Nothing here depends on vector data: a caller may issue these loads
+// before it has waited for the vector the chunk multiplies.
+template <typename VT, int K>
+__device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restrict__ rowptr,
+                                           const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                           ChunkRegs<VT, K> &g) {
+    using AT = typename AccumType<VT>::T;
+    const int tid = threadIdx.x;
+    const int nr = d.y - d.x;
+#pragma unroll
+    for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
+        if (m * kBlock <= nr) g.rbv[m] = rowptr[d.x + min(tid + m * kBlock, nr)];
+#pragma unroll
+    for (int m = 0; m < kProdPerThread; ++m) {
+        const int pidx = tid + m * kBlock;
+        const int jc = min(d.z + pidx / K, d.w - 1);
+        g.cj[m] = col[jc];
+        g.a[m] = (AT)load_value(val, jc);
+    }
+}
+
+// The rest of a plain chunk: gathers of x, products and row pointers to LDS,
+// then phase 2 (one thread per row for k <= 2, per (row, column) for k >= 4,
+// stored order, four products read ahead) and the epilogue.
+template <typename VT, int K, bool REC, bool COH>
+__device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
+                                             double *__restrict__ y, int q, const double *__restrict__ yq2,
+                                             const RecArgs &rec, ChunkLds<VT, K> &lds) {
+    using AT = typename AccumType<VT>::T;
+    constexpr int NP = kProdPerThread;
+    const int tid = threadIdx.x;
+    const int r0 = d.x, j0 = d.z;
+    const int nr = d.y - d.x;
+    AT xv[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
+#pragma unroll
+    for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
+        if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = g.rbv[m];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) lds.prod[tid + m * kBlock] = g.a[m] * xv[m];
+    lds_barrier();
+    if constexpr (K <= 2) {
+        for (int r = tid; r < nr; r += kBlock) {
+            const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
+            AT sum[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) sum[c] = (AT)0;
+            int i = s;
+            for (; i + 4 <= e; i += 4) {
+                AT pr[4][K];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < K; ++c) pr[u][c] = lds.prod[(i + u) * K + c];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < K; ++c) sum[c] = sum[c] + pr[u][c];
+            }
+            for (; i < e; ++i) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) sum[c] = sum[c] + lds.prod[i * K + c];
+            }
+            double v[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) v[c] = (double)sum[c];
+            store_row<K, REC, COH>(r0 + r, v, x, y, q, yq2, rec);
+        }
+    } else {
+        const int nout = nr * K;
+        for (int o = tid; o < nout; o += kBlock) {
+            const int r = o / K, c = o % K;
+            const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
+            AT sum = (AT)0;
+            int i = s;
+            for (; i + 4 <= e; i += 4) {
+                const AT p0 = lds.prod[i * K + c], p1 = lds.prod[(i + 1) * K + c];
+                const AT p2 = lds.prod[(i + 2) * K + c], p3 = lds.prod[(i + 3) * K + c];
+                sum = sum + p0;
+                sum = sum + p1;
+                sum = sum + p2;
+                sum = sum + p3;
+            }
+            for (; i < e; ++i) sum = sum + lds.prod[i * K + c];
+            put<COH>(y + (int64_t)(r0 + r) * K + c, (double)sum);
+        }
+    }
+    lds_barrier();  // LDS is reused by the next chunk
+}
+
 // One chunk d = (r0, r1, j0, j1): rows [r0, r1) with stored nonzeros
 // [j0, j1), at most chunk_nnz(K) of them and at most kChunkRows rows, or a
 // single longer row.
@@ -156,103 +267,25 @@ __device__ __forceinline__ void chunk_pass(const int4 d, const int32_t *__restri
                                            const double *__restrict__ yq2, const RecArgs &rec,
                                            ChunkLds<VT, K> &lds) {
     using AT = typename AccumType<VT>::T;
-    constexpr int NP = kProdPerThread;
     static_assert(K == 1 || K == 2 || !REC, "the recurrence epilogue handles k <= 2");
     const int tid = threadIdx.x;
     const int r0 = d.x, r1 = d.y, j0 = d.z, j1 = d.w;
-    if (j1 - j0 <= chunk_nnz(K)) {
-        if (j1 == j0) {  // rows without stored entries: y = 0 (uniform branch)
-            for (int r = r0 + tid; r < r1; r += kBlock) {
-                double v[K];
+    if (plain_chunk<K>(d)) {
+        ChunkRegs<VT, K> g;
+        chunk_load<VT, K>(d, rowptr, col, val, g);
+        chunk_finish<VT, K, REC, COH>(d, g, x, y, q, yq2, rec, lds);
+    } else if (j1 == j0) {  // rows without stored entries: y = 0 (uniform branch)
+        for (int r = r0 + tid; r < r1; r += kBlock) {
+            double v[K];
 #pragma unroll
-                for (int c = 0; c < K; ++c) v[c] = 0.0;
-                if constexpr (K <= 2) {
-                    store_row<K, REC, COH>(r, v, x, y, q, yq2, rec);
-                } else {
+            for (int c = 0; c < K; ++c) v[c] = 0.0;
+            if constexpr (K <= 2) {
+                store_row<K, REC, COH>(r, v, x, y, q, yq2, rec);
+            } else {
 #pragma unroll
-                    for (int c = 0; c < K; ++c) put<COH>(y + (int64_t)r * K + c, 0.0);
-                }
-            }
-            return;
-        }
-        const int nr = r1 - r0;
-        // row pointers rowptr[r0 .. r1] (uniform guards: no divergence)
-        constexpr int NRB = (kChunkRows + 1 + kBlock - 1) / kBlock;
-        int rbv[NRB];
-#pragma unroll
-        for (int m = 0; m < NRB; ++m)
-            if (m * kBlock <= nr) rbv[m] = rowptr[r0 + min(tid + m * kBlock, nr)];
-        // phase 1: every load is unconditional (slots past the chunk re-read
-        // its last entry, whose product phase 2 never reads), so a thread
-        // issues all its val/col loads, then all its gathers, without waiting
-        // in between
-        int cj[NP];
-        AT a[NP];
-#pragma unroll
-        for (int m = 0; m < NP; ++m) {
-            const int pidx = tid + m * kBlock;
-            const int jc = min(j0 + pidx / K, j1 - 1);
-            cj[m] = col[jc];
-            a[m] = (AT)load_value(val, jc);
-        }
-        AT xv[NP];
-#pragma unroll
-        for (int m = 0; m < NP; ++m) xv[m] = (AT)x[(int64_t)cj[m] * K + ((tid + m * kBlock) % K)];
-#pragma unroll
-        for (int m = 0; m < NRB; ++m)
-            if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = rbv[m];
-#pragma unroll
-        for (int m = 0; m < NP; ++m) lds.prod[tid + m * kBlock] = a[m] * xv[m];
-        lds_barrier();
-        if constexpr (K <= 2) {
-            // phase 2: one thread per row, all K columns, stored order
-            for (int r = tid; r < nr; r += kBlock) {
-                const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
-                AT sum[K];
-#pragma unroll
-                for (int c = 0; c < K; ++c) sum[c] = (AT)0;
-                int i = s;
-                for (; i + 4 <= e; i += 4) {
-                    AT pr[4][K];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int c = 0; c < K; ++c) pr[u][c] = lds.prod[(i + u) * K + c];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int c = 0; c < K; ++c) sum[c] = sum[c] + pr[u][c];
-                }
-                for (; i < e; ++i) {
-#pragma unroll
-                    for (int c = 0; c < K; ++c) sum[c] = sum[c] + lds.prod[i * K + c];
-                }
-                double v[K];
-#pragma unroll
-                for (int c = 0; c < K; ++c) v[c] = (double)sum[c];
-                store_row<K, REC, COH>(r0 + r, v, x, y, q, yq2, rec);
-            }
-        } else {
-            // phase 2: one thread per (row, column), stored order
-            const int nout = nr * K;
-            for (int o = tid; o < nout; o += kBlock) {
-                const int r = o / K, c = o % K;
-                const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
-                AT sum = (AT)0;
-                int i = s;
-                for (; i + 4 <= e; i += 4) {
-                    const AT p0 = lds.prod[i * K + c], p1 = lds.prod[(i + 1) * K + c];
-                    const AT p2 = lds.prod[(i + 2) * K + c], p3 = lds.prod[(i + 3) * K + c];
-                    sum = sum + p0;
-                    sum = sum + p1;
-                    sum = sum + p2;
-                    sum = sum + p3;
-                }
-                for (; i < e; ++i) sum = sum + lds.prod[i * K + c];
-                put<COH>(y + (int64_t)(r0 + r) * K + c, (double)sum);
+                for (int c = 0; c < K; ++c) put<COH>(y + (int64_t)r * K + c, 0.0);
             }
         }
-        lds_barrier();  // LDS is reused by the next chunk
     } else {
         // a single row longer than a chunk: thread (slot, c) accumulates
         // nonzeros slot, slot + S, ... of column c; then a tree over slots

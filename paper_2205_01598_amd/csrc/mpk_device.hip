@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     // needs no co-residency.  The last workgroup to leave resets the counters.
     __shared__ int s_sub, s_ok;
     __shared__ int s_next[2];
+    __shared__ ChunkLds<VT, K> lds;
     const int nS = a.nstreams;
     const int stream = blockIdx.x % nS;
     const int in_stream = (gridDim.x - stream + nS - 1) / nS;
@@ -307,21 +308,34 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         const int w = a.work[base + t];
         const int tile = w >> 6;
         const int q = (w & 63) + 1;
+        const int c0 = a.tile_chunk[tile], c1 = a.tile_chunk[tile + 1];
+        const int4 d0 = a.chunk[c0];
+        // The first chunk's matrix entries and row pointers do not depend on
+        // the flags: they are loaded before the wait, so their latency and
+        // the polling overlap.  The barriers around the poll order only LDS
+        // (s_ok) and leave those loads in flight.
+        const bool pre = plain_chunk<K>(d0);
+        ChunkRegs<VT, K> g;
+        if (pre) chunk_load<VT, K>(d0, a.rowptr, a.col, val, g);
         if (q > 1) {
             if (threadIdx.x == 0) s_ok = 1;
-            __syncthreads();
+            lds_barrier();
             if (threadIdx.x < 64) {
                 const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep3 + 6 * tile, a, base + t);
                 if (!ok && threadIdx.x == 0) s_ok = 0;
             }
-            __syncthreads();
+            lds_barrier();
             if (!s_ok) break;
         }
         const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
-        chunks_body<VT, K, REC, true>(a.tile_chunk[tile], a.tile_chunk[tile + 1], a.chunk, a.rowptr, a.col,
-                                      val, xin, yout, q, yq2, rec);
+        if (pre)
+            chunk_finish<VT, K, REC, true>(d0, g, xin, yout, q, yq2, rec, lds);
+        else
+            chunk_pass<VT, K, REC, true>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+        for (int c = c0 + 1; c < c1; ++c)
+            chunk_pass<VT, K, REC, true>(a.chunk[c], a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
         // The next ticket is taken only now: a workgroup never holds a ticket
         // it is not working on, so no ticket waits behind an idle one.
         uint32_t kn = 0;
