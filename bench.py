@@ -318,7 +318,7 @@ def main():
     log(f"plan: {plan.info()['n_levels']} levels in {plan_s:.1f}s")
     # the same plan with the breadth-first levels on the GPU
     t0 = time.time()
-    pdev = Plan(A, p, 256 << 20, root_mode=1, upload=False, levels_on_device=1)
+    pdev = Plan(A, p, 256 << 20, root_mode=1, upload=False, plan_on_device=1)
     plan_dev_s = time.time() - t0
     assert np.array_equal(pdev.arrays()[0], plan.arrays()[0])
     plan_phases = {"host_levels": [round(v, 3) for v in plan.info()["phase_seconds"]],
@@ -463,7 +463,7 @@ def main():
         "baseline_gflops": round(flop / t_base / 1e6, 1),
         "plan_seconds": round(plan_s, 2),
         "plan_spmv_equivalents": round(plan_s / (t_base / p * 1e-3), 0),
-        "plan_seconds_levels_on_device": round(plan_dev_s, 2),
+        "plan_seconds_plan_on_device": round(plan_dev_s, 2),
         "plan_phase_seconds": plan_phases,
         "sync_ladder": ladder,
         "other_powers": other,

@@ -92,8 +92,11 @@ typedef struct mpk_options {
                                  of every level group are cut into 8 slices and slice s is run by
                                  workgroups with blockIdx % 8 == s (the XCD they are dispatched to
                                  on MI355X), so a tile meets the same L2 at every power */
-    int32_t levels_on_device; /* 1: breadth-first levels and root search of mpk_plan_create run on the
-                                 current GPU (same result as the host, bit for bit); 0 (default): host */
+    int32_t plan_on_device;   /* 1: mpk_plan_create uses the current GPU: graph, levels (root search,
+                                 breadth-first levels) and the renumbered matrix for a pattern with
+                                 sorted symmetric rows; for other patterns the host builds the graph
+                                 and renumbers, the GPU only levels.  Same results as the host, bit
+                                 for bit.  0 (default): host only */
     int32_t force_acquire;    /* 1: every dependency wait ends with an agent-scope acquire fence even
                                  when mpk_run could do without it (see mpk_plan_info.line_closed_deps) */
     int32_t reserved[3];
@@ -169,9 +172,9 @@ void mpk_options_default(mpk_options *opt);
  * groups under Eq. (5) with budget floor(f*C) bytes and b_nz = sizeof(value)+4
  * bytes per nonzero (12 for FP64, Sec. 3.1), the Lp diagonal order of the
  * groups (Fig. 6), and device tiles with their point-to-point dependency
- * ranges (Sec. 4.3).  Host work only (no GPU call), except the
- * breadth-first levels with opt->levels_on_device = 1, which use the current
- * GPU and free its memory before returning.  The CSR is
+ * ranges (Sec. 4.3).  Host work only (no GPU call), except with
+ * opt->plan_on_device = 1, where graph, levels and renumbering use the
+ * current GPU, whose memory is freed before returning.  The CSR is
  * copied; the caller may free it on return.  p in [1, MPK_MAX_POWER],
  * cache_bytes > 0.  *out receives a new plan (free with mpk_plan_destroy).
  * Errors: MPK_ERR_ARG, MPK_ERR_CSR, MPK_ERR_OOM, MPK_ERR_UNSUPPORTED

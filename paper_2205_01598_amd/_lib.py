@@ -42,7 +42,7 @@ class mpk_options(ctypes.Structure):
                 ("tile_nnz", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
                 ("skew", ctypes.c_int32), ("xcd_streams", ctypes.c_int32),
-                ("levels_on_device", ctypes.c_int32), ("force_acquire", ctypes.c_int32),
+                ("plan_on_device", ctypes.c_int32), ("force_acquire", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 3)]
 
 

@@ -38,14 +38,14 @@ def build(verbose: bool = False) -> str:
         [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "mpk_device.hip"),
          "-o", os.path.join(BUILD, "mpk_device.o")],
         [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "mlp.hip"), "-o", os.path.join(BUILD, "mlp.o")],
-        [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "levels_device.hip"),
-         "-o", os.path.join(BUILD, "levels_device.o")],
+        [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "plan_device.hip"),
+         "-o", os.path.join(BUILD, "plan_device.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
     _run(["g++", "-shared", "-fopenmp", "-o", tmp, os.path.join(BUILD, "plan.o"),
-          os.path.join(BUILD, "mpk_device.o"), os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "levels_device.o"),
+          os.path.join(BUILD, "mpk_device.o"), os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "plan_device.o"),
           f"-L{ROCM}/lib", "-lamdhip64",
           f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB)

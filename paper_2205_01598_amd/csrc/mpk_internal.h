@@ -96,11 +96,19 @@ int32_t chunk_nnz_host(int32_t k);
 // rows per chunk cap: bounds the chunk's row-pointer slice kept in LDS
 constexpr int32_t kChunkRows = 1024;
 
-// Breadth-first levels and root on the current GPU (levels_device.hip): the
+// Breadth-first levels and root on the current GPU (plan_device.hip): the
 // same root, permutation and level pointers as the host planner, from the
 // undirected graph (ptr[n+1], adj[ptr[n]], lists ascending, no diagonal).
 mpk_status device_bfs_levels(int64_t n, const int64_t *ptr, const int32_t *adj, int32_t root_mode, int64_t *root_out,
                              std::vector<int32_t> &perm, std::vector<int32_t> &level_ptr);
+
+// Graph, levels and renumbered matrix P A P^T on the current GPU
+// (plan_device.hip) for a pattern whose rows are sorted and symmetric; the
+// same results as the host planner.  *handled = false (and nothing filled)
+// for other patterns.  phase_seconds[0..2]: graph, levels, renumbering.
+mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, std::vector<int32_t> &perm,
+                       std::vector<int32_t> &level_ptr, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+                       std::vector<double> &val, bool *handled, double *phase_seconds);
 
 // Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
 int32_t bytes_per_nnz(int32_t dtype);

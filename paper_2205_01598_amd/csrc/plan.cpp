@@ -656,7 +656,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.reserved0 != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
-    if (opt.levels_on_device != 0 && opt.levels_on_device != 1) return fail(MPK_ERR_ARG, "levels_on_device must be 0 or 1");
+    if (opt.plan_on_device != 0 && opt.plan_on_device != 1) return fail(MPK_ERR_ARG, "plan_on_device must be 0 or 1");
     if (opt.force_acquire != 0 && opt.force_acquire != 1) return fail(MPK_ERR_ARG, "force_acquire must be 0 or 1");
 
     const int64_t n = A->n;
@@ -671,20 +671,29 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
         auto now = [] { return std::chrono::steady_clock::now(); };
         auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
         auto ta = now();
-        Graph g;
-        build_graph(A, g);
-        auto tb = now();
-        hp.root = 0;
-        if (opt.levels_on_device) {
-            st = device_bfs_levels(n, g.ptr.data(), g.adj.data(), opt.root_mode, &hp.root, hp.perm, hp.level_ptr);
+        // On the GPU: graph, levels and P A P^T for a sorted symmetric pattern;
+        // otherwise the host builds the graph (and, on the GPU, only the levels).
+        bool on_device = false;
+        if (opt.plan_on_device) {
+            st = device_plan(A, opt.root_mode, &hp.root, hp.perm, hp.level_ptr, hp.rowptr, hp.col, hp.val, &on_device,
+                             hp.phase_seconds);
             if (st != MPK_OK) return st;
-        } else {
-            if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
-            bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
         }
-        hp.phase_seconds[0] = secs(ta, tb);
-        hp.phase_seconds[1] = secs(tb, now());
-        { Graph().adj.swap(g.adj); }
+        if (!on_device) {
+            Graph g;
+            build_graph(A, g);
+            auto tb = now();
+            hp.root = 0;
+            if (opt.plan_on_device) {
+                st = device_bfs_levels(n, g.ptr.data(), g.adj.data(), opt.root_mode, &hp.root, hp.perm, hp.level_ptr);
+                if (st != MPK_OK) return st;
+            } else {
+                if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
+                bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+            }
+            hp.phase_seconds[0] = secs(ta, tb);
+            hp.phase_seconds[1] = secs(tb, now());
+        }
         hp.iperm.assign(n, 0);
         for (int64_t i = 0; i < n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
         const int64_t L = (int64_t)hp.level_ptr.size() - 1;
@@ -704,32 +713,34 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
 
         auto tr0 = std::chrono::steady_clock::now();
         // ---- renumbered matrix P A P^T -------------------------------------------------
-        hp.rowptr.assign(n + 1, 0);
-        for (int64_t r = 0; r < n; ++r) {
-            int64_t o = hp.perm[r];
-            hp.rowptr[r + 1] = hp.rowptr[r] + (int32_t)(A->rowptr[o + 1] - A->rowptr[o]);
-        }
-        hp.col.resize(A->nnz);
-        hp.val.resize(A->nnz);
-#pragma omp parallel
-        {
-            std::vector<std::pair<int32_t, double>> buf;
-#pragma omp for schedule(dynamic, 2048)
+        if (!on_device) {
+            hp.rowptr.assign(n + 1, 0);
             for (int64_t r = 0; r < n; ++r) {
                 int64_t o = hp.perm[r];
-                int64_t a = A->rowptr[o], b = A->rowptr[o + 1];
-                buf.resize(b - a);
-                for (int64_t j = a; j < b; ++j) buf[j - a] = {hp.iperm[A->col[j]], A->val[j]};
-                std::stable_sort(buf.begin(), buf.end(),
-                                 [](const auto &x, const auto &y) { return x.first < y.first; });
-                int64_t out = hp.rowptr[r];
-                for (size_t t = 0; t < buf.size(); ++t) {
-                    hp.col[out + t] = buf[t].first;
-                    hp.val[out + t] = buf[t].second;
+                hp.rowptr[r + 1] = hp.rowptr[r] + (int32_t)(A->rowptr[o + 1] - A->rowptr[o]);
+            }
+            hp.col.resize(A->nnz);
+            hp.val.resize(A->nnz);
+#pragma omp parallel
+            {
+                std::vector<std::pair<int32_t, double>> buf;
+#pragma omp for schedule(dynamic, 2048)
+                for (int64_t r = 0; r < n; ++r) {
+                    int64_t o = hp.perm[r];
+                    int64_t a = A->rowptr[o], b = A->rowptr[o + 1];
+                    buf.resize(b - a);
+                    for (int64_t j = a; j < b; ++j) buf[j - a] = {hp.iperm[A->col[j]], A->val[j]};
+                    std::stable_sort(buf.begin(), buf.end(),
+                                     [](const auto &x, const auto &y) { return x.first < y.first; });
+                    int64_t out = hp.rowptr[r];
+                    for (size_t t = 0; t < buf.size(); ++t) {
+                        hp.col[out + t] = buf[t].first;
+                        hp.val[out + t] = buf[t].second;
+                    }
                 }
             }
+            hp.phase_seconds[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tr0).count();
         }
-        hp.phase_seconds[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tr0).count();
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");
     }

@@ -1,0 +1,597 @@
+// Preprocessing on the GPU: graph of the pattern, breadth-first levels (Eq. 3)
+// and the renumbered matrix, with the same results as the host planner.
+//
+// Levels come in the same Cuthill-McKee discovery order as on the host: each
+// vertex of level i, taken in new order, numbers its not yet numbered
+// neighbours in ascending original index.
+//
+// One level of the frontier order[a, b) is expanded by three kernels:
+//   claim    owner[v] = smallest frontier position adjacent to v (atomic
+//            minimum; owner only ever decreases, so a plain read that is
+//            already <= f makes the atomic unnecessary);
+//   count    every frontier vertex counts the neighbours it owns, and a
+//            workgroup scan gives its offset inside the workgroup;
+//   scatter  after a scan of the workgroup totals, every frontier vertex
+//            writes the neighbours it owns, in adjacency order, at
+//            b + its offset.
+// The host reads back the new frontier's size (4 bytes) per level.  An empty
+// frontier with vertices left starts a new component at the smallest
+// unnumbered index (a reduction), as a new level.  owner[v] is INT32_MAX for
+// an unnumbered vertex and a position below the current frontier otherwise.
+//
+// The George-Liu pseudo-peripheral search runs component-restricted sweeps of
+// the same expansion and picks the smallest-degree vertex of the last level
+// (lowest index on ties) with a 64-bit atomic minimum of (degree, index).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mpk_internal.h"
+
+namespace mpk {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void set_root(int32_t *order, int32_t *owner, int64_t pos, const int32_t *root) {
+    const int32_t r = *root;
+    order[pos] = r;
+    owner[r] = -1;
+}
+
+__global__ void claim(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                      const int32_t *__restrict__ order, int64_t a, int64_t b, int32_t *owner) {
+    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (f >= b) return;
+    const int32_t u = order[f];
+    for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
+        int32_t *w = owner + adj[j];
+        if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)f)
+            atomicMin(w, (int32_t)f);
+    }
+}
+
+// per frontier vertex: owned-neighbour count; exclusive offset inside the
+// workgroup in local[]; workgroup total in blocksum[]
+__global__ void count(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                      const int32_t *__restrict__ order, const int32_t *__restrict__ owner, int64_t a, int64_t b,
+                      int32_t *__restrict__ local, int32_t *__restrict__ blocksum) {
+    __shared__ int32_t s[kThreads];
+    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    int32_t c = 0;
+    if (f < b) {
+        const int32_t u = order[f];
+        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) c += owner[adj[j]] == (int32_t)f;
+    }
+    s[threadIdx.x] = c;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the workgroup
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (f < b) local[f - a] = s[threadIdx.x] - c;
+    if (threadIdx.x == kThreads - 1) blocksum[blockIdx.x] = s[kThreads - 1];
+}
+
+// one workgroup: exclusive scan of nb workgroup totals in place, grand total
+// to *total
+__global__ void scan_blocks(int32_t *blocksum, int64_t nb, int32_t *total) {
+    __shared__ int32_t s[kThreads];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = i < nb ? blocksum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < kThreads; d <<= 1) {
+            const int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) blocksum[i] = carry + s[threadIdx.x] - v;
+        const int32_t step = s[kThreads - 1];
+        __syncthreads();
+        carry += step;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                        int32_t *__restrict__ order, const int32_t *__restrict__ owner, int64_t a, int64_t b,
+                        const int32_t *__restrict__ local, const int32_t *__restrict__ blocksum) {
+    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (f >= b) return;
+    const int32_t u = order[f];
+    int64_t o = b + blocksum[blockIdx.x] + local[f - a];
+    for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
+        const int32_t v = adj[j];
+        if (owner[v] == (int32_t)f) order[o++] = v;
+    }
+}
+
+// smallest index v with owner[v] == INT32_MAX (n if none)
+__global__ void first_unnumbered(const int32_t *__restrict__ owner, int64_t n, int32_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (owner[i] == INT32_MAX) {
+            atomicMin(out, (int32_t)i);
+            return;  // later indices of this thread are larger
+        }
+}
+
+// (degree, index) minimum over order[a, b)
+__global__ void min_degree(const int64_t *__restrict__ ptr, const int32_t *__restrict__ order, int64_t a, int64_t b,
+                           unsigned long long *out) {
+    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (f >= b) return;
+    const int32_t v = order[f];
+    const unsigned long long key = ((unsigned long long)(ptr[v + 1] - ptr[v]) << 32) | (uint32_t)v;
+    atomicMin(out, key);
+}
+
+struct DeviceGraph {
+    int64_t n = 0;
+    int64_t *ptr = nullptr;
+    int32_t *adj = nullptr, *owner = nullptr, *order = nullptr, *local = nullptr, *blocksum = nullptr,
+            *scalar = nullptr;
+    unsigned long long *key = nullptr;
+    std::vector<void *> allocs;
+    ~DeviceGraph() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+#define LV_TRY(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? MPK_ERR_OOM : MPK_ERR_HIP,                         \
+                        std::string("device levels: ") + #expr + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(DeviceGraph &g, T **p, int64_t count) {
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+    if (e == hipSuccess) g.allocs.push_back(*p);
+    return e;
+}
+
+inline unsigned grid_for(int64_t items) { return (unsigned)((items + kThreads - 1) / kThreads); }
+
+// Expands levels from order[start, start+1) (the root already placed) until
+// the component is exhausted; appends level ends to lptr.  Returns the
+// position after the component in *end.
+mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> &lptr, int64_t *end) {
+    int64_t a = start, b = start + 1;
+    while (a < b) {
+        const int64_t F = b - a;
+        const unsigned nb = grid_for(F);
+        hipLaunchKernelGGL(claim, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, a, b, g.owner);
+        hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, a, b, g.local,
+                           g.blocksum);
+        hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, (int64_t)nb, g.scalar);
+        hipLaunchKernelGGL(scatter, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, a, b, g.local,
+                           g.blocksum);
+        LV_TRY(hipGetLastError());
+        int32_t next = 0;
+        LV_TRY(hipMemcpy(&next, g.scalar, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (next < 0 || b + next > g.n) return fail(MPK_ERR_HIP, "device levels: inconsistent frontier size");
+        lptr.push_back((int32_t)b);
+        a = b;
+        b += next;
+    }
+    *end = a;
+    return MPK_OK;
+}
+
+mpk_status place_root(DeviceGraph &g, int64_t pos, int32_t root) {
+    LV_TRY(hipMemcpy(g.scalar, &root, sizeof(int32_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(set_root, dim3(1), dim3(1), 0, 0, g.order, g.owner, pos, g.scalar);
+    LV_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status reset_owner(DeviceGraph &g) {
+    hipLaunchKernelGGL(fill_i32, dim3(1024), dim3(kThreads), 0, 0, g.owner, g.n, (int32_t)INT32_MAX);
+    LV_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// work buffers of the level expansion (the graph itself is set by the caller)
+mpk_status alloc_bfs(DeviceGraph &g) {
+    const int64_t n = g.n;
+    LV_TRY(dalloc(g, &g.owner, n));
+    LV_TRY(dalloc(g, &g.order, n));
+    LV_TRY(dalloc(g, &g.local, n));
+    LV_TRY(dalloc(g, &g.blocksum, (n + kThreads - 1) / kThreads));
+    LV_TRY(dalloc(g, &g.scalar, 1));
+    LV_TRY(dalloc(g, &g.key, 1));
+    return MPK_OK;
+}
+
+// root, levels and the new order (left in g.order) of the graph in g
+mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, std::vector<int32_t> &level_ptr) {
+    const int64_t n = g.n;
+
+    // ---- root: vertex 0, or George-Liu from vertex 0 -------------------------------
+    int32_t root = 0;
+    if (root_mode == 1) {
+        std::vector<int32_t> lp;
+        auto sweep = [&](int32_t r, int64_t *ecc) -> mpk_status {
+            mpk_status st;
+            if ((st = reset_owner(g)) != MPK_OK) return st;
+            if ((st = place_root(g, 0, r)) != MPK_OK) return st;
+            lp.assign(1, 0);
+            int64_t end = 0;
+            if ((st = expand_component(g, 0, lp, &end)) != MPK_OK) return st;
+            *ecc = (int64_t)lp.size() - 2;
+            return MPK_OK;
+        };
+        int64_t ecc = 0;
+        mpk_status st = sweep(root, &ecc);
+        if (st != MPK_OK) return st;
+        for (;;) {
+            const unsigned long long init = ~0ull;
+            LV_TRY(hipMemcpy(g.key, &init, sizeof(init), hipMemcpyHostToDevice));
+            const int64_t a = lp[lp.size() - 2], b = lp.back();
+            hipLaunchKernelGGL(min_degree, dim3(grid_for(b - a)), dim3(kThreads), 0, 0, g.ptr, g.order, a, b, g.key);
+            LV_TRY(hipGetLastError());
+            unsigned long long key = 0;
+            LV_TRY(hipMemcpy(&key, g.key, sizeof(key), hipMemcpyDeviceToHost));
+            const int32_t cand = (int32_t)(key & 0xffffffffu);
+            int64_t e2 = 0;
+            if ((st = sweep(cand, &e2)) != MPK_OK) return st;
+            if (e2 > ecc) {
+                root = cand;
+                ecc = e2;
+            } else {
+                break;
+            }
+        }
+    }
+    *root_out = root;
+
+    // ---- levels of the whole graph: root's component, then the others --------------
+    mpk_status st;
+    if ((st = reset_owner(g)) != MPK_OK) return st;
+    if ((st = place_root(g, 0, root)) != MPK_OK) return st;
+    int64_t pos = 0;
+    if ((st = expand_component(g, 0, level_ptr, &pos)) != MPK_OK) return st;
+    while (pos < n) {
+        const int32_t none = (int32_t)n;
+        LV_TRY(hipMemcpy(g.scalar, &none, sizeof(int32_t), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(first_unnumbered, dim3(1024), dim3(kThreads), 0, 0, g.owner, n, g.scalar);
+        LV_TRY(hipGetLastError());
+        int32_t next_root = 0;
+        LV_TRY(hipMemcpy(&next_root, g.scalar, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (next_root < 0 || next_root >= n) return fail(MPK_ERR_HIP, "device levels: lost vertices");
+        if ((st = place_root(g, pos, next_root)) != MPK_OK) return st;
+        if ((st = expand_component(g, pos, level_ptr, &pos)) != MPK_OK) return st;
+    }
+    return MPK_OK;
+}
+
+}  // namespace
+
+mpk_status device_bfs_levels(int64_t n, const int64_t *ptr, const int32_t *adj, int32_t root_mode, int64_t *root_out,
+                             std::vector<int32_t> &perm, std::vector<int32_t> &level_ptr) {
+    perm.assign(n, 0);
+    level_ptr.assign(1, 0);
+    *root_out = 0;
+    if (n == 0) return MPK_OK;
+    DeviceGraph g;
+    g.n = n;
+    const int64_t m = ptr[n];
+    LV_TRY(dalloc(g, &g.ptr, n + 1));
+    LV_TRY(dalloc(g, &g.adj, m));
+    mpk_status st = alloc_bfs(g);
+    if (st != MPK_OK) return st;
+    LV_TRY(hipMemcpy(g.ptr, ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    if (m > 0) LV_TRY(hipMemcpy(g.adj, adj, sizeof(int32_t) * m, hipMemcpyHostToDevice));
+    if ((st = bfs_on_device(g, root_mode, root_out, level_ptr)) != MPK_OK) return st;
+    LV_TRY(hipMemcpy(perm.data(), g.order, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    return MPK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph and renumbering
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int64_t kSortOnDevice = 256;  // rows up to this length are sorted by one thread
+
+__global__ void rows_sorted(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n, int32_t *ok) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t j = rp[u] + 1; j < rp[u + 1]; ++j)
+            if (col[j] < col[j - 1]) {
+                atomicMin(ok, 0);
+                break;
+            }
+}
+
+// every stored (u, v), v != u, has a stored (v, u) (rows sorted)
+__global__ void pattern_symmetric(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+                                  int32_t *ok) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+            const int32_t v = col[j];
+            if (v == u) continue;
+            int64_t lo = rp[v], hi = rp[v + 1];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < u) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo == rp[v + 1] || col[lo] != u) {
+                atomicMin(ok, 0);
+                return;
+            }
+        }
+    }
+}
+
+// adjacency of a symmetric sorted pattern: the row without the diagonal and
+// without repeated entries (count, then write at the scanned offsets)
+__global__ void adjacency_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+                                int64_t *__restrict__ cnt) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m = 0, last = -1;
+        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+            const int32_t v = col[j];
+            if (v == u || v == last) continue;
+            ++m;
+            last = v;
+        }
+        cnt[u] = m;
+    }
+}
+
+__global__ void adjacency_write(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+                                const int64_t *__restrict__ aptr, int32_t *__restrict__ adj) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = aptr[u], last = -1;
+        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+            const int32_t v = col[j];
+            if (v == u || v == last) continue;
+            adj[o++] = v;
+            last = v;
+        }
+    }
+}
+
+// exclusive scan of n int64 values: out[0..n], out[n] = total
+__global__ void scan_local(const int64_t *__restrict__ in, int64_t n, int64_t *__restrict__ out,
+                           int64_t *__restrict__ bsum) {
+    __shared__ int64_t s[kThreads];
+    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    const int64_t v = i < n ? in[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == kThreads - 1) bsum[blockIdx.x] = s[kThreads - 1];
+}
+
+__global__ void scan_sums(int64_t *bsum, int64_t nb) {  // one workgroup; bsum[nb] = total
+    __shared__ int64_t s[kThreads];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nb ? bsum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < kThreads; d <<= 1) {
+            const int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + s[threadIdx.x] - v;
+        const int64_t step = s[kThreads - 1];
+        __syncthreads();
+        carry += step;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ void scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ bsum, int64_t nb) {
+    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) out[i] += bsum[blockIdx.x];
+    if (i == 0) out[n] = bsum[nb];
+}
+
+__global__ void inverse_perm(const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ iperm) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        iperm[perm[r]] = (int32_t)r;
+}
+
+__global__ void new_lengths(const int64_t *__restrict__ rp, const int32_t *__restrict__ perm, int64_t n,
+                            int64_t *__restrict__ len) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = perm[r];
+        len[r] = rp[o + 1] - rp[o];
+    }
+}
+
+// row r of P A P^T: row perm[r] of A with columns mapped through iperm,
+// sorted by new column with a stable insertion sort (rows longer than
+// kSortOnDevice are listed for the host instead)
+__global__ void renumber_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                              const double *__restrict__ val, const int32_t *__restrict__ perm,
+                              const int32_t *__restrict__ iperm, const int64_t *__restrict__ nrp, int64_t n,
+                              int32_t *__restrict__ ncol, double *__restrict__ nval, int32_t *long_rows,
+                              int32_t *n_long) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = perm[r];
+        const int64_t a = rp[o], len = rp[o + 1] - a, base = nrp[r];
+        int32_t *c = ncol + base;
+        double *v = nval + base;
+        for (int64_t j = 0; j < len; ++j) {
+            c[j] = iperm[col[a + j]];
+            v[j] = val[a + j];
+        }
+        if (len > kSortOnDevice) {
+            long_rows[atomicAdd(n_long, 1)] = (int32_t)r;
+            continue;
+        }
+        for (int64_t i = 1; i < len; ++i) {
+            const int32_t kc = c[i];
+            const double kv = v[i];
+            int64_t k = i - 1;
+            while (k >= 0 && c[k] > kc) {
+                c[k + 1] = c[k];
+                v[k + 1] = v[k];
+                --k;
+            }
+            c[k + 1] = kc;
+            v[k + 1] = kv;
+        }
+    }
+}
+
+mpk_status scan_on_device(DeviceGraph &g, const int64_t *in, int64_t n, int64_t *out) {
+    const int64_t nb = std::max<int64_t>(1, (n + kThreads - 1) / kThreads);
+    int64_t *bsum = nullptr;
+    LV_TRY(dalloc(g, &bsum, nb + 1));
+    hipLaunchKernelGGL(scan_local, dim3((unsigned)nb), dim3(kThreads), 0, 0, in, n, out, bsum);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kThreads), 0, 0, bsum, nb);
+    hipLaunchKernelGGL(scan_add, dim3((unsigned)nb), dim3(kThreads), 0, 0, out, n, bsum, nb);
+    LV_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+}  // namespace
+
+mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, std::vector<int32_t> &perm,
+                       std::vector<int32_t> &level_ptr, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
+                       std::vector<double> &val, bool *handled, double *phase_seconds) {
+    *handled = false;
+    const int64_t n = A->n, nnz = A->nnz;
+    if (n == 0) return MPK_OK;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+    const auto t0 = now();
+    DeviceGraph g;
+    g.n = n;
+    int64_t *drp = nullptr;
+    int32_t *dcol = nullptr, *flag = nullptr;
+    LV_TRY(dalloc(g, &drp, n + 1));
+    LV_TRY(dalloc(g, &dcol, nnz));
+    LV_TRY(dalloc(g, &flag, 1));
+    LV_TRY(hipMemcpy(drp, A->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    if (nnz > 0) LV_TRY(hipMemcpy(dcol, A->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    // ---- graph: only for sorted symmetric patterns (else the host builds it) ---------
+    const int32_t one = 1;
+    LV_TRY(hipMemcpy(flag, &one, sizeof(int32_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(rows_sorted, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
+    hipLaunchKernelGGL(pattern_symmetric, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
+    LV_TRY(hipGetLastError());
+    int32_t ok = 0;
+    LV_TRY(hipMemcpy(&ok, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (!ok) return MPK_OK;  // not handled: the caller takes the host path
+    int64_t *cnt = nullptr;
+    LV_TRY(dalloc(g, &cnt, n));
+    LV_TRY(dalloc(g, &g.ptr, n + 1));
+    hipLaunchKernelGGL(adjacency_count, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, cnt);
+    LV_TRY(hipGetLastError());
+    mpk_status st = scan_on_device(g, cnt, n, g.ptr);
+    if (st != MPK_OK) return st;
+    int64_t m = 0;
+    LV_TRY(hipMemcpy(&m, g.ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    LV_TRY(dalloc(g, &g.adj, m));
+    hipLaunchKernelGGL(adjacency_write, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, g.ptr, g.adj);
+    LV_TRY(hipGetLastError());
+    LV_TRY(hipDeviceSynchronize());
+    const auto t1 = now();
+    // ---- levels ----------------------------------------------------------------------
+    if ((st = alloc_bfs(g)) != MPK_OK) return st;
+    level_ptr.assign(1, 0);
+    if ((st = bfs_on_device(g, root_mode, root_out, level_ptr)) != MPK_OK) return st;
+    LV_TRY(hipDeviceSynchronize());
+    const auto t2 = now();
+    // ---- renumbered matrix P A P^T ---------------------------------------------------
+    double *dval = nullptr, *nval = nullptr;
+    int32_t *iperm = nullptr, *ncol = nullptr, *long_rows = nullptr;
+    int64_t *nrp = nullptr;
+    LV_TRY(dalloc(g, &dval, nnz));
+    LV_TRY(dalloc(g, &nval, nnz));
+    LV_TRY(dalloc(g, &ncol, nnz));
+    LV_TRY(dalloc(g, &iperm, n));
+    LV_TRY(dalloc(g, &nrp, n + 1));
+    LV_TRY(dalloc(g, &long_rows, n));
+    if (nnz > 0) LV_TRY(hipMemcpy(dval, A->val, sizeof(double) * nnz, hipMemcpyHostToDevice));
+    const int32_t zero = 0;
+    LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(inverse_perm, dim3(2048), dim3(kThreads), 0, 0, g.order, n, iperm);
+    hipLaunchKernelGGL(new_lengths, dim3(2048), dim3(kThreads), 0, 0, drp, g.order, n, cnt);
+    LV_TRY(hipGetLastError());
+    if ((st = scan_on_device(g, cnt, n, nrp)) != MPK_OK) return st;
+    hipLaunchKernelGGL(renumber_rows, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, dval, g.order, iperm, nrp, n, ncol,
+                       nval, long_rows, flag);
+    LV_TRY(hipGetLastError());
+    perm.assign(n, 0);
+    std::vector<int64_t> rp64(n + 1);
+    rowptr.resize(n + 1);
+    col.resize(nnz);
+    val.resize(nnz);
+    int32_t n_long = 0;
+    LV_TRY(hipMemcpy(perm.data(), g.order, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    LV_TRY(hipMemcpy(rp64.data(), nrp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (nnz > 0) {
+        LV_TRY(hipMemcpy(col.data(), ncol, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+        LV_TRY(hipMemcpy(val.data(), nval, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
+    LV_TRY(hipMemcpy(&n_long, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i <= n; ++i) rowptr[i] = (int32_t)rp64[i];
+    if (n_long > 0) {
+        std::vector<int32_t> rows(n_long);
+        LV_TRY(hipMemcpy(rows.data(), long_rows, sizeof(int32_t) * n_long, hipMemcpyDeviceToHost));
+#pragma omp parallel
+        {
+            std::vector<std::pair<int32_t, double>> buf;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t i = 0; i < n_long; ++i) {
+                const int64_t a = rowptr[rows[i]], b = rowptr[rows[i] + 1];
+                buf.resize(b - a);
+                for (int64_t j = a; j < b; ++j) buf[j - a] = {col[j], val[j]};
+                std::stable_sort(buf.begin(), buf.end(),
+                                 [](const auto &x, const auto &y) { return x.first < y.first; });
+                for (int64_t j = a; j < b; ++j) {
+                    col[j] = buf[j - a].first;
+                    val[j] = buf[j - a].second;
+                }
+            }
+        }
+    }
+    const auto t3 = now();
+    phase_seconds[0] = secs(t0, t1);
+    phase_seconds[1] = secs(t1, t2);
+    phase_seconds[2] = secs(t2, t3);
+    *handled = true;
+    return MPK_OK;
+}
+
+}  // namespace mpk

@@ -1,7 +1,10 @@
-"""Breadth-first levels on the GPU (levels_on_device = 1): the root, the
-permutation and the level pointers must equal the host planner's and the
-oracle's bit for bit (Eq. 3, discovery order inside a level, components
-started at the smallest unnumbered index)."""
+"""Preprocessing on the GPU (plan_on_device = 1): graph, breadth-first
+levels and the renumbered matrix.  The root, the permutation, the level
+pointers, the groups, the schedule and P A P^T must equal the host
+planner's bit for bit, and the levels the oracle's (Eq. 3, discovery order
+inside a level, components started at the smallest unnumbered index).
+Sorted symmetric patterns take the all-device path; the others build the
+graph on the host and level it on the GPU."""
 import numpy as np
 import pytest
 
@@ -38,17 +41,31 @@ def _cases():
     rng = np.random.default_rng(5)
     yield "irregular", W.random_small_csr(300, 0.01, rng, symmetric_pattern=False, empty_rows=0.2, duplicates=0.1)
     yield "single", W.CSR(1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([2.0]))
+    # arrow: one full row and column, so one renumbered row exceeds the
+    # device sort length and is sorted on the host
+    n = 1500
+    rows = np.concatenate([np.zeros(n, np.int64), np.arange(1, n), np.arange(1, n)])
+    cols = np.concatenate([np.arange(n), np.zeros(n - 1, np.int64), np.arange(1, n)])
+    order = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    Arw = W.CSR(n, np.cumsum(rp), cols[order].astype(np.int32), np.random.default_rng(1).uniform(-1, 1, len(rows)))
+    yield "arrow", W.relabel(Arw, np.random.default_rng(2).permutation(n))
+    yield "symmetric_duplicates", W.random_small_csr(400, 0.02, np.random.default_rng(7), symmetric_pattern=True,
+                                                     empty_rows=0.1, duplicates=0.2)
 
 
 @pytest.mark.parametrize("root_mode", [0, 1])
 @pytest.mark.parametrize("name,A", list(_cases()), ids=[c[0] for c in _cases()])
-def test_device_levels_match_host_and_oracle(name, A, root_mode):
+def test_device_plan_matches_host_and_oracle(name, A, root_mode):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     host = Plan(A, 4, 1 << 20, upload=False, root_mode=root_mode)
-    dev = Plan(A, 4, 1 << 20, upload=False, root_mode=root_mode, levels_on_device=1)
+    dev = Plan(A, 4, 1 << 20, upload=False, root_mode=root_mode, plan_on_device=1)
     assert dev.info()["root"] == host.info()["root"]
     for a, b in zip(dev.arrays(), host.arrays()):
+        assert np.array_equal(a, b)
+    for a, b in zip(dev.matrix(), host.matrix()):
         assert np.array_equal(a, b)
     perm, lp = O.bfs_levels(A, root_mode)
     assert np.array_equal(dev.arrays()[0], perm) and np.array_equal(dev.arrays()[1], lp)
@@ -61,7 +78,7 @@ def test_device_levels_large_and_run():
         pytest.skip("no GPU")
     A, _ = W.stencil_27pt_random(48, seed=1)
     host = Plan(A, 6, 4 << 20, upload=False, root_mode=1)
-    dev = Plan(A, 6, 4 << 20, root_mode=1, levels_on_device=1)
+    dev = Plan(A, 6, 4 << 20, root_mode=1, plan_on_device=1)
     for a, b in zip(dev.arrays(), host.arrays()):
         assert np.array_equal(a, b)
     perm = dev.arrays()[0].astype(np.int64)

@@ -253,7 +253,7 @@ def test_plan_rejects_bad_input():
     with pytest.raises(MpkError, match="MPK_ERR_ARG"):
         Plan(A, 2, 1000, upload=False, reserved0=1)
     with pytest.raises(MpkError, match="MPK_ERR_ARG"):
-        Plan(A, 2, 1000, upload=False, levels_on_device=2)
+        Plan(A, 2, 1000, upload=False, plan_on_device=2)
     with pytest.raises(MpkError, match="MPK_ERR_UNSUPPORTED"):
         Plan(A, 2, 1000, upload=False, nrhs=4, val_dtype="bf16")
 
