@@ -9,8 +9,8 @@
 // flattened with c fastest), issuing all its val/col loads and then all its
 // gathers without waiting in between, and writes them to LDS together with
 // the chunk's row pointers.  Phase 2: after a barrier, a thread sums one
-// row's products (k <= 2: all columns of the row; k >= 4: one column) in
-// stored order, reading four products ahead, and applies the epilogue.  A
+// row's products (k = 1) or one column of a row (k >= 2) in stored order,
+// reading four products ahead, and applies the epilogue.  A
 // chunk is described by (first row, end row, first nonzero, end nonzero).
 #pragma once
 
@@ -188,7 +188,7 @@ __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restri
 }
 
 // The rest of a plain chunk: gathers of x, products and row pointers to LDS,
-// then phase 2 (one thread per row for k <= 2, per (row, column) for k >= 4,
+// then phase 2 (one thread per row for k = 1, per (row, column) for k >= 2,
 // stored order, four products read ahead) and the epilogue.
 template <typename VT, int K, bool REC, bool COH>
 __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
@@ -208,7 +208,28 @@ __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K
 #pragma unroll
     for (int m = 0; m < NP; ++m) lds.prod[tid + m * kBlock] = g.a[m] * xv[m];
     lds_barrier();
-    if constexpr (K <= 2) {
+    if constexpr (K == 2) {
+        // one lane per (row, column): the lanes of a wavefront store and load
+        // consecutive entries (a lane per row would leave every store
+        // instruction half of each line); stored order per column
+        const int nout = nr * 2;
+        for (int o = tid; o < nout; o += kBlock) {
+            const int r = o >> 1, c = o & 1;
+            const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
+            AT sum = (AT)0;
+            int i = s;
+            for (; i + 4 <= e; i += 4) {
+                const AT p0 = lds.prod[i * 2 + c], p1 = lds.prod[(i + 1) * 2 + c];
+                const AT p2 = lds.prod[(i + 2) * 2 + c], p3 = lds.prod[(i + 3) * 2 + c];
+                sum = sum + p0;
+                sum = sum + p1;
+                sum = sum + p2;
+                sum = sum + p3;
+            }
+            for (; i < e; ++i) sum = sum + lds.prod[i * 2 + c];
+            store_col2<REC, COH>(r0 + r, c, (double)sum, x, y, q, yq2, rec);
+        }
+    } else if constexpr (K == 1) {
         for (int r = tid; r < nr; r += kBlock) {
             const int s = lds.rb[r] - j0, e = lds.rb[r + 1] - j0;
             AT sum[K];
@@ -255,6 +276,44 @@ __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K
         }
     }
     lds_barrier();  // LDS is reused by the next chunk
+}
+
+// Epilogue for one output entry (row r, column c) of k = 2 columns, held by
+// lane pair (2r', 2r'+1) of a wavefront; the complex accumulator update
+// takes the partner column from the other lane of the pair.  Every lane of
+// the pair must call it together.
+template <bool REC, bool COH>
+__device__ __forceinline__ void store_col2(int64_t r, int c, double v, const double *__restrict__ x,
+                                           double *__restrict__ y, int q, const double *__restrict__ yq2,
+                                           const RecArgs &rec) {
+    const int64_t i = r * 2 + c;
+    if constexpr (REC) {
+        const double al = rec.alpha[q - 1], be = rec.beta[q - 1], ga = rec.gamma[q - 1];
+        v *= al;
+        if (be != 0.0) v += be * x[i];
+        if (ga != 0.0) v += ga * yq2[i];
+    }
+    put<COH>(y + i, v);
+    if constexpr (REC) {
+        if (rec.acc) {
+            const bool start = rec.start_acc && q == 1;
+            if (rec.complex_pairs) {
+                const double vo = __shfl_xor(v, 1);
+                const double cr = rec.coef_re[q - 1], ci = rec.coef_im[q - 1];
+                double a;
+                if (start) {
+                    const double xs = x[i], xo = __shfl_xor(xs, 1);
+                    a = c == 0 ? rec.c0_re * xs - rec.c0_im * xo : rec.c0_re * xs + rec.c0_im * xo;
+                } else {
+                    a = get<COH>(rec.acc + i);
+                }
+                put<COH>(rec.acc + i, a + (c == 0 ? cr * v - ci * vo : cr * v + ci * vo));
+            } else {
+                const double a = start ? rec.c0_re * x[i] : get<COH>(rec.acc + i);
+                put<COH>(rec.acc + i, a + rec.coef_re[q - 1] * v);
+            }
+        }
+    }
 }
 
 // One chunk d = (r0, r1, j0, j1): rows [r0, r1) with stored nonzeros
