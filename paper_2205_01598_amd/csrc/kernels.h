@@ -146,6 +146,61 @@ __device__ __forceinline__ void store_row(int64_t r, const double *v_in, const d
     }
 }
 
+// Epilogue for one output entry (row r, column c) of k = 2 columns, held by
+// lane pair (2r', 2r'+1) of a wavefront; the complex accumulator update
+// takes the partner column from the other lane of the pair.  Every lane of
+// the pair must call it together.  The operands it reads from memory (own
+// entry of y_{q-1}, of y_{q-2}, of the running sum) are loaded by
+// col2_operands, which a caller may issue early to hide their latency.
+struct Col2Ops {
+    double xs, yq, acc;
+};
+
+template <bool COH>
+__device__ __forceinline__ Col2Ops col2_operands(int64_t r, int c, const double *__restrict__ x,
+                                                 const double *__restrict__ yq2, int q, const RecArgs &rec) {
+    const int64_t i = r * 2 + c;
+    const bool start = rec.start_acc && q == 1;
+    Col2Ops o;
+    o.xs = (rec.beta[q - 1] != 0.0 || (rec.acc && start)) ? x[i] : 0.0;
+    o.yq = rec.gamma[q - 1] != 0.0 ? yq2[i] : 0.0;
+    o.acc = (rec.acc && !start) ? get<COH>(rec.acc + i) : 0.0;
+    return o;
+}
+
+template <bool REC, bool COH>
+__device__ __forceinline__ void store_col2(int64_t r, int c, double v, const Col2Ops &op, double *__restrict__ y,
+                                           int q, const RecArgs &rec) {
+    const int64_t i = r * 2 + c;
+    if constexpr (REC) {
+        const double al = rec.alpha[q - 1], be = rec.beta[q - 1], ga = rec.gamma[q - 1];
+        v *= al;
+        if (be != 0.0) v += be * op.xs;
+        if (ga != 0.0) v += ga * op.yq;
+    }
+    put<COH>(y + i, v);
+    if constexpr (REC) {
+        if (rec.acc) {
+            const bool start = rec.start_acc && q == 1;
+            if (rec.complex_pairs) {
+                const double vo = __shfl_xor(v, 1);
+                const double cr = rec.coef_re[q - 1], ci = rec.coef_im[q - 1];
+                double a;
+                if (start) {
+                    const double xo = __shfl_xor(op.xs, 1);
+                    a = c == 0 ? rec.c0_re * op.xs - rec.c0_im * xo : rec.c0_re * op.xs + rec.c0_im * xo;
+                } else {
+                    a = op.acc;
+                }
+                put<COH>(rec.acc + i, a + (c == 0 ? cr * v - ci * vo : cr * v + ci * vo));
+            } else {
+                const double a = start ? rec.c0_re * op.xs : op.acc;
+                put<COH>(rec.acc + i, a + rec.coef_re[q - 1] * v);
+            }
+        }
+    }
+}
+
 // Registers of one chunk between its matrix loads and its gathers.
 template <typename VT, int K>
 struct ChunkRegs {
@@ -202,6 +257,11 @@ __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K
     AT xv[NP];
 #pragma unroll
     for (int m = 0; m < NP; ++m) xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
+    // k = 2 with the recurrence: the epilogue operands of this thread's first
+    // output travel with the gathers instead of after the sums
+    Col2Ops pre{};
+    if constexpr (K == 2 && REC)
+        if (tid < nr * 2) pre = col2_operands<COH>(r0 + (tid >> 1), tid & 1, x, yq2, q, rec);
 #pragma unroll
     for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
         if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = g.rbv[m];
@@ -227,7 +287,9 @@ __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K
                 sum = sum + p3;
             }
             for (; i < e; ++i) sum = sum + lds.prod[i * 2 + c];
-            store_col2<REC, COH>(r0 + r, c, (double)sum, x, y, q, yq2, rec);
+            Col2Ops op{};
+            if constexpr (REC) op = o == tid ? pre : col2_operands<COH>(r0 + r, c, x, yq2, q, rec);
+            store_col2<REC, COH>(r0 + r, c, (double)sum, op, y, q, rec);
         }
     } else if constexpr (K == 1) {
         for (int r = tid; r < nr; r += kBlock) {
@@ -276,44 +338,6 @@ __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K
         }
     }
     lds_barrier();  // LDS is reused by the next chunk
-}
-
-// Epilogue for one output entry (row r, column c) of k = 2 columns, held by
-// lane pair (2r', 2r'+1) of a wavefront; the complex accumulator update
-// takes the partner column from the other lane of the pair.  Every lane of
-// the pair must call it together.
-template <bool REC, bool COH>
-__device__ __forceinline__ void store_col2(int64_t r, int c, double v, const double *__restrict__ x,
-                                           double *__restrict__ y, int q, const double *__restrict__ yq2,
-                                           const RecArgs &rec) {
-    const int64_t i = r * 2 + c;
-    if constexpr (REC) {
-        const double al = rec.alpha[q - 1], be = rec.beta[q - 1], ga = rec.gamma[q - 1];
-        v *= al;
-        if (be != 0.0) v += be * x[i];
-        if (ga != 0.0) v += ga * yq2[i];
-    }
-    put<COH>(y + i, v);
-    if constexpr (REC) {
-        if (rec.acc) {
-            const bool start = rec.start_acc && q == 1;
-            if (rec.complex_pairs) {
-                const double vo = __shfl_xor(v, 1);
-                const double cr = rec.coef_re[q - 1], ci = rec.coef_im[q - 1];
-                double a;
-                if (start) {
-                    const double xs = x[i], xo = __shfl_xor(xs, 1);
-                    a = c == 0 ? rec.c0_re * xs - rec.c0_im * xo : rec.c0_re * xs + rec.c0_im * xo;
-                } else {
-                    a = get<COH>(rec.acc + i);
-                }
-                put<COH>(rec.acc + i, a + (c == 0 ? cr * v - ci * vo : cr * v + ci * vo));
-            } else {
-                const double a = start ? rec.c0_re * x[i] : get<COH>(rec.acc + i);
-                put<COH>(rec.acc + i, a + rec.coef_re[q - 1] * v);
-            }
-        }
-    }
 }
 
 // One chunk d = (r0, r1, j0, j1): rows [r0, r1) with stored nonzeros
