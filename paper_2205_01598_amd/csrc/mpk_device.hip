@@ -313,8 +313,9 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         // The first chunk's matrix entries and row pointers do not depend on
         // the flags: they are loaded before the wait, so their latency and
         // the polling overlap.  The barriers around the poll order only LDS
-        // (s_ok) and leave those loads in flight.
-        const bool pre = plain_chunk<K>(d0);
+        // (s_ok) and leave those loads in flight.  For k >= 4 the registers
+        // held across the wait cost more occupancy than the overlap gains.
+        const bool pre = K <= 2 && plain_chunk<K>(d0);
         ChunkRegs<VT, K> g;
         if (pre) chunk_load<VT, K>(d0, a.rowptr, a.col, val, g);
         if (q > 1) {
