@@ -295,3 +295,112 @@ def cheb_propagate_real(A, x, coeffs) -> np.ndarray:
         acc = acc + coeffs[k] * v_next
         v_prev, v = v, v_next
     return acc
+
+
+# ----------------------------------------------------------------------------
+# recursive refinement of bulky levels (Sec. 4.4)
+# ----------------------------------------------------------------------------
+
+def _undirected_adjacency(A):
+    """Neighbour lists of the graph of A + A^T without the diagonal (lists of
+    original indices)."""
+    import scipy.sparse as sp
+
+    S = sp.csr_matrix((np.ones(A.nnz), np.asarray(A.col, np.int64), np.asarray(A.rowptr, np.int64)),
+                      shape=(A.n, A.n))
+    U = ((S + S.T) != 0).tocsr()
+    U.setdiag(False)
+    U.eliminate_zeros()
+    U.sort_indices()
+    return [U.indices[U.indptr[v]:U.indptr[v + 1]] for v in range(A.n)]
+
+
+def _subgraph_levels(rows, adj, pos):
+    """Breadth-first levels of the subgraph induced by ``rows`` (original
+    indices listed in the current numbering).  Root: the first row; each
+    vertex, taken in the new order, appends its unvisited neighbours inside
+    the subgraph in ascending current position; when the frontier is empty
+    the first unvisited row (in current order) starts the next level.
+    Returns (order, level_ptr) with order a list of original indices."""
+    inside = set(int(v) for v in rows)
+    seen = set()
+    order, lptr = [], [0]
+    scan = 0
+    while len(order) < len(rows):
+        while int(rows[scan]) in seen:
+            scan += 1
+        root = int(rows[scan])
+        seen.add(root)
+        frontier = [root]
+        order.append(root)
+        lptr.append(len(order))
+        while frontier:
+            nxt = []
+            for u in frontier:
+                nb = sorted((int(v) for v in adj[u] if int(v) in inside and int(v) not in seen), key=lambda v: pos[v])
+                for v in nb:
+                    seen.add(v)
+                    nxt.append(v)
+            if nxt:
+                order.extend(nxt)
+                lptr.append(len(order))
+            frontier = nxt
+    return order, lptr
+
+
+def refine_levels(A, perm, level_ptr, p: int, cache_bytes: int, f: float = 0.5, bytes_per_nnz: int = 12,
+                  stages: int = 1, row_weight=None):
+    """Recursive level refinement (Sec. 4.4), up to ``stages`` stages (s_m).
+
+    At stage s the levels are grouped by Eq. (5) (``level_groups``); every
+    maximal run of consecutive groups that violate Eq. (5) (single bulky
+    levels) is replaced by the breadth-first levels of the subgraph it
+    induces (``_subgraph_levels``), which are grouped and refined again at
+    stage s+1, as long as s+1 <= stages.  Groups that satisfy Eq. (5), and
+    violating ones at the last stage, are kept as they are.  Nonzeros per
+    level count the whole rows of A.
+
+    ``row_weight`` (per original row) replaces the row lengths in Eq. (5),
+    e.g. ones for the vertex-counting cache of the Sec. 4.4 example.
+
+    Returns (perm, unit_ptr, unit_stage): the final numbering (new -> old),
+    the row boundaries of the final groups ("units", int64[U+1]) in that
+    numbering, and the stage each unit comes from.
+    """
+    rowlen = (np.diff(np.asarray(A.rowptr, dtype=np.int64)) if row_weight is None
+              else np.asarray(row_weight, dtype=np.int64))
+    adj = _undirected_adjacency(A)
+    pos = np.empty(A.n, dtype=np.int64)
+    pos[np.asarray(perm, dtype=np.int64)] = np.arange(A.n)
+    budget = int(np.floor(float(f) * float(cache_bytes)))
+
+    def refine(rows, lptr, stage):
+        lnnz = np.array([int(rowlen[np.asarray(rows[lptr[i]:lptr[i + 1]], dtype=np.int64)].sum())
+                         for i in range(len(lptr) - 1)], dtype=np.int64)
+        gptr = level_groups(lnnz, p, cache_bytes, f, bytes_per_nnz)
+        gnnz = [int(lnnz[gptr[i]:gptr[i + 1]].sum()) for i in range(len(gptr) - 1)]
+        violates = [(p + 1) * g * bytes_per_nnz >= budget for g in gnnz]
+        order, units = [], []
+        i, G = 0, len(gptr) - 1
+        while i < G:
+            if stage >= stages or not violates[i]:
+                part = list(rows[lptr[gptr[i]]:lptr[gptr[i + 1]]])
+                order.extend(part)
+                units.append((len(part), stage))
+                i += 1
+                continue
+            j = i
+            while j < G and violates[j]:
+                j += 1
+            region = rows[lptr[gptr[i]]:lptr[gptr[j]]]
+            sub_order, sub_lptr = _subgraph_levels(region, adj, pos)
+            o2, u2 = refine(sub_order, sub_lptr, stage + 1)
+            order.extend(o2)
+            units.extend(u2)
+            i = j
+        return order, units
+
+    order, units = refine([int(v) for v in perm], [int(v) for v in level_ptr], 0)
+    unit_ptr = np.zeros(len(units) + 1, dtype=np.int64)
+    unit_ptr[1:] = np.cumsum([u[0] for u in units])
+    return (np.asarray(order, dtype=np.int32), unit_ptr, np.asarray([u[1] for u in units], dtype=np.int64))

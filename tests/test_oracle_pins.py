@@ -488,3 +488,105 @@ def test_heat_propagate_vs_expm(order):
     assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref) + 1e-15
     # heat flow contracts the state
     assert np.linalg.norm(out) < np.linalg.norm(x)
+
+
+# ----------------------------------------------------------------------------
+# recursive level refinement (Sec. 4.4)
+# ----------------------------------------------------------------------------
+
+def test_refinement_worked_example():
+    # Sec. 4.4: with a cache of at most six vertices, T(4)..T(6) (levels 6-8
+    # of the 8x8 2d-7pt example, 22 vertices) induce a subgraph with eight
+    # BFS levels whose level groups all satisfy Eq. (5): the process stops
+    A = W.stencil_2d(8, 7)
+    perm, lp = O.bfs_levels(A, 0)
+    ones = np.ones(A.n, np.int64)
+    fp, up, us = O.refine_levels(A, perm, lp, p=1, cache_bytes=300, stages=1, row_weight=ones)
+    sizes = np.diff(up)
+    assert np.all(2 * sizes * 12 < 150)                       # every unit fits "six vertices"
+    region = us == 1
+    assert sizes[region].sum() == 7 + 8 + 7
+    # the refined rows are exactly those of levels 6-8, placed where they were
+    lo, hi = lp[6], lp[9]
+    assert sorted(fp[lo:hi].tolist()) == sorted(perm[lo:hi].tolist())
+    assert np.array_equal(fp[:lo], perm[:lo]) and np.array_equal(fp[hi:], perm[hi:])
+    # eight BFS levels: graph distances inside the subgraph from its first row
+    sub = _induced_distances(A, fp[lo:hi])
+    assert sub.max() + 1 == 8
+    # with s_m = 0 nothing changes and the units are the level groups
+    fp0, up0, us0 = O.refine_levels(A, perm, lp, p=1, cache_bytes=300, stages=0, row_weight=ones)
+    assert np.array_equal(fp0, perm) and np.all(us0 == 0)
+    assert np.diff(up0).tolist() == [6, 4, 5, 6, 7, 8, 7, 6, 5, 4, 6]
+
+
+def _induced_distances(A, rows):
+    """Unweighted distances inside the subgraph induced by ``rows`` from
+    rows[0] (scipy), for the rows in the given order; unreachable rows get a
+    distance one past the largest reachable one."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path as sp_path
+
+    rows = np.asarray(rows, dtype=np.int64)
+    S = sp.csr_matrix((np.ones(A.nnz), np.asarray(A.col, np.int64), np.asarray(A.rowptr, np.int64)),
+                      shape=(A.n, A.n))
+    U = ((S + S.T) != 0).astype(np.float64).tocsr()[rows][:, rows]
+    d = sp_path(U, unweighted=True, directed=False, indices=0)
+    d[np.isinf(d)] = np.nanmax(np.where(np.isinf(d), np.nan, d)) + 1
+    return d.astype(np.int64)
+
+
+@pytest.mark.parametrize("case", ["2d5pt", "27pt", "rgg"])
+def test_refinement_invariants(case):
+    if case == "2d5pt":
+        A, p, C = W.stencil_2d(40, 5), 4, 6000
+    elif case == "27pt":
+        A, p, C = W.stencil_27pt_random(12, seed=3)[0], 3, 40000
+    else:
+        A, p, C = W.random_geometric(3000, 10.0, seed=2)[0], 2, 3000
+    perm, lp = O.bfs_levels(A, 1)
+    rowlen = np.diff(A.rowptr)
+    budget = int(np.floor(0.5 * C))
+    fp, up, us = O.refine_levels(A, perm, lp, p, C, stages=1)
+    assert sorted(fp.tolist()) == list(range(A.n))
+    assert up[0] == 0 and up[-1] == A.n and np.all(np.diff(up) > 0)
+    unit_nnz = np.array([rowlen[fp[a:b]].sum() for a, b in zip(up[:-1], up[1:])])
+    gptr = O.level_groups(O.level_nnz(A, perm, lp), p, C)
+    group_rows = lp[gptr]
+    viol = [(p + 1) * O.level_nnz(A, perm, lp)[gptr[i]:gptr[i + 1]].sum() * 12 >= budget
+            for i in range(len(gptr) - 1)]
+    assert any(viol)                                           # the case exercises refinement
+    # stage-0 units are the non-violating groups, unchanged
+    st0 = [(a, b) for a, b, s in zip(up[:-1], up[1:], us) if s == 0]
+    for i in range(len(gptr) - 1):
+        if not viol[i]:
+            a, b = group_rows[i], group_rows[i + 1]
+            assert (a, b) in st0 and np.array_equal(fp[a:b], perm[a:b])
+    # every refined region keeps its rows, and inside it the subgraph
+    # distances from its first row never decrease and units are whole levels
+    i = 0
+    while i < len(gptr) - 1:
+        if not viol[i]:
+            i += 1
+            continue
+        j = i
+        while j < len(gptr) - 1 and viol[j]:
+            j += 1
+        a, b = group_rows[i], group_rows[j]
+        assert sorted(fp[a:b].tolist()) == sorted(perm[a:b].tolist())
+        d = _induced_distances(A, fp[a:b])
+        assert np.all(np.diff(d) >= 0)
+        for ua, ub in zip(up[:-1], up[1:]):
+            if a <= ua < b:
+                assert ub <= b
+                if ub < b:
+                    assert d[ub - a] > d[ub - 1 - a]          # a unit ends where a level ends
+        i = j
+    # every unit satisfies Eq. (5) unless it is a single level at the last stage
+    for (a, b), s, nz in zip(zip(up[:-1], up[1:]), us, unit_nnz):
+        if (p + 1) * nz * 12 >= budget:
+            if s == 0:
+                li = np.searchsorted(lp, a)
+                assert lp[li] == a and lp[li + 1] == b          # a single stage-0 level
+            else:
+                d = _induced_distances(A, fp[a:b])
+                assert s == 1                                    # last stage (s_m = 1)
