@@ -11,7 +11,8 @@ MPK GFLOP/s (2 nnz p / t), speedup over the faster of two tuned baselines
 (p SpMV launches on the matrix as given, and on the BFS-renumbered matrix),
 roofline fraction of the persistent kernel against 8 TB/s HBM on algorithmic
 bytes, mixed-precision (FP32 / BF16 values) throughput and error against the
-FP64 run, the synchronisation ladder, and the FP64 CPU oracle timed on the
+FP64 run, the synchronisation ladder, refined plans (recursion, s_m = 1, 2),
+and the FP64 CPU oracle timed on the
 host (the only use of the oracle here).  Other workloads: 64^2 Laplacian,
 Anderson 128^3 and heat-equation 160^3 Chebyshev propagation, multi-RHS RGG,
 the learned tuner.
@@ -383,6 +384,29 @@ def main():
               "p2p_flags_ms": round(ms, 4), "baseline_ms": round(t_base, 4)}
     log(f"sync ladder: {ladder}")
 
+    # ---- recursive level refinement (Sec. 4.4) on the same matrix and launch options ----
+    recursion = {"unrefined": {"ms": round(ms, 4), "level_groups": G, "violating_groups": info["violating_groups"]}}
+    if not args.only_main:
+        for sm in (1, 2):
+            t0 = time.time()
+            pr = Plan(A, p, cfg["cache"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile"],
+                      recursion_stages=sm)
+            ps = time.time() - t0
+            rperm = pr.arrays()[0].astype(np.int64)
+            Xr = torch.from_numpy(np.ascontiguousarray(x[rperm])).to(dev)
+            tr = timed(torch, lambda: pr.run(Xr, Y), 10, 2)
+            pr.status()
+            Yr = np.empty((p, n))
+            Yr[:, rperm] = Y.cpu().numpy()
+            ri = pr.info()
+            recursion[f"s_m={sm}"] = {"ms": round(tr, 4), "gflops": round(flop / tr / 1e6, 1),
+                                      "vs_unrefined": round(ms / tr, 3), "units": ri["n_units"],
+                                      "max_stage": ri["max_stage"], "dep_ranges_per_tile":
+                                      round(ri["n_dep_ranges"] / ri["n_tiles"], 2), "plan_seconds": round(ps, 2),
+                                      "max_rel_diff_vs_unrefined": float(f"{max(rel_errs(Yr, Yh)):.3e}")}
+            del pr, Xr
+        log(f"recursion: {recursion}")
+
     # ---- other powers ----------------------------------------------------------------
     other = {}
     for q in (() if args.only_main else (4, 6)):
@@ -466,6 +490,7 @@ def main():
         "plan_seconds_plan_on_device": round(plan_dev_s, 2),
         "plan_phase_seconds": plan_phases,
         "sync_ladder": ladder,
+        "recursion": recursion,
         "other_powers": other,
         "mixed_precision": mixed,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -99,7 +99,13 @@ typedef struct mpk_options {
                                  for bit.  0 (default): host only */
     int32_t force_acquire;    /* 1: every dependency wait ends with an agent-scope acquire fence even
                                  when mpk_run could do without it (see mpk_plan_info.line_closed_deps) */
-    int32_t reserved[3];
+    int32_t recursion_stages; /* s_m of Sec. 4.4: maximal runs of consecutive level groups that
+                                 violate Eq. (5) are replaced by the breadth-first levels of the
+                                 subgraph they induce, grouped again, up to this many stages.
+                                 0 (default): no refinement.  A refined plan orders its tickets by
+                                 a longest-path wavefront number over per-tile dependency lists and
+                                 cannot be retuned (the numbering depends on p and C). */
+    int32_t reserved[2];
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */
@@ -130,6 +136,10 @@ typedef struct mpk_plan_info {
                                  power is read before all its rows are final, so no cache holds a
                                  stale copy; the accumulator is read with agent-scope loads. */
     int32_t last_run_fenced;  /* the last mpk_run used the acquire fence: 1, did not: 0, no run: -1 */
+    int32_t recursive;        /* 1: refined levels (recursion_stages > 0, Sec. 4.4) */
+    int32_t max_stage;        /* deepest refinement stage of a final group (0: none refined) */
+    int64_t n_units;          /* final level groups: G, or the groups of the refined numbering */
+    int64_t n_dep_ranges;     /* refined plans: tile ranges in all dependency lists together */
 } mpk_plan_info;
 
 /* Three-term recurrence epilogue for mpk_run / mpk_run_baseline (Sec. 7,
@@ -223,6 +233,23 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
  * a vector slice (they may reach one tile into groups g-2 and g+2), which
  * mpk_run uses when it skips the acquire fence. */
 mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges, int32_t line_closed);
+
+/* Refined plans only (recursion_stages > 0, Sec. 4.4), host copies; any
+ * pointer may be NULL.  The refined numbering (perm of mpk_plan_arrays) lists
+ * the final level groups ("units") one after the other:
+ *   unit_ptr[n_units+1]  first new row of every unit
+ *   unit_stage[n_units]  stage at which the unit was formed: 0 = a group of
+ *                        the original levels that satisfies Eq. (5), s >= 1 =
+ *                        a group of the levels of a subgraph refined s times
+ *   dep_ptr[n_tiles+1]   first range of every tile's dependency list
+ *   dep_rng[2*n_dep_ranges] inclusive tile ranges (lo, hi): before power q a
+ *                        tile waits for power q-1 of these tiles, which hold
+ *                        every row it reads and every row that shares a
+ *                        128-byte line of a vector slice with them.
+ * Level groups and the schedule of mpk_plan_arrays describe the unrefined
+ * (stage-0) levels.  Errors: MPK_ERR_STATE for an unrefined plan. */
+mpk_status mpk_plan_units(const mpk_plan *plan, int32_t *unit_ptr, int32_t *unit_stage, int32_t *dep_ptr,
+                          int32_t *dep_rng);
 
 /* Matrix and level features for the learned tuner, host, MPK_NUM_FEATURES
  * doubles: log10 N, log10 nnz, mean / standard deviation / log2(max+1) of the

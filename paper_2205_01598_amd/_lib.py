@@ -43,7 +43,7 @@ class mpk_options(ctypes.Structure):
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
                 ("skew", ctypes.c_int32), ("xcd_streams", ctypes.c_int32),
                 ("plan_on_device", ctypes.c_int32), ("force_acquire", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("recursion_stages", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class mpk_plan_info(ctypes.Structure):
@@ -55,7 +55,9 @@ class mpk_plan_info(ctypes.Structure):
                 ("workgroups", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("tile_nnz", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
                 ("plan_seconds", ctypes.c_double), ("phase_seconds", ctypes.c_double * 4),
-                ("line_closed_deps", ctypes.c_int32), ("last_run_fenced", ctypes.c_int32)]
+                ("line_closed_deps", ctypes.c_int32), ("last_run_fenced", ctypes.c_int32),
+                ("recursive", ctypes.c_int32), ("max_stage", ctypes.c_int32),
+                ("n_units", ctypes.c_int64), ("n_dep_ranges", ctypes.c_int64)]
 
 
 class mpk_recurrence(ctypes.Structure):
@@ -81,6 +83,7 @@ SIGNATURES = {
     "mpk_plan_matrix": (ctypes.c_int32, [_P, _I64P, _I32P, _F64P]),
     "mpk_plan_tiles": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
     "mpk_plan_tile_deps": (ctypes.c_int32, [_P, _I32P, ctypes.c_int32]),
+    "mpk_plan_units": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),
     "mpk_plan_features": (ctypes.c_int32, [_P, _F64P]),
     "mpk_plan_upload": (ctypes.c_int32, [_P]),
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),

@@ -54,6 +54,7 @@ struct mpk_plan {
     int32_t *d_perm = nullptr;
     int32_t *d_chunk = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;  // d_chunk: int4 per chunk
     int32_t *d_dep3x = nullptr;
+    int32_t *d_dep_ptr = nullptr, *d_dep_rng = nullptr;  // refined plans: per-tile range lists
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
     std::vector<void *> allocs;
 };
@@ -221,6 +222,11 @@ struct MpkArgs {
     int32_t stream_ptr[kMaxStreams + 1];
     int64_t watchdog;
     int32_t acquire;  // 1: agent-scope acquire fence after every dependency wait
+    // refined plans: tile t waits for the inclusive tile ranges
+    // dep_rng[2k..2k+1], k in [dep_ptr[t], dep_ptr[t+1]), instead of dep3
+    const int32_t *dep_ptr;
+    const int32_t *dep_rng;
+    int32_t dep_lists;
 };
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
@@ -230,19 +236,17 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Executed by one full wavefront.  Waits until the flags of the three tile
-// ranges d[0..1], d[2..3], d[4..5] (inclusive, lo > hi = empty) all hold
-// `epoch`, 64 flags per vector load; returns false if the watchdog expired or
+// Executed by one full wavefront: polls until the flags f[j] of `total`
+// indices j = index(i), i < total, all hold `epoch`, 64 flags per vector
+// load.  Returns false if the watchdog expired (and reports the ticket) or
 // another workgroup already reported a timeout in this run.
-__device__ bool wait_flags(const uint32_t *f, const int32_t *d, const MpkArgs &a, int ticket) {
+template <typename Index>
+__device__ bool poll_flags(const uint32_t *f, int total, Index index, const MpkArgs &a, int ticket) {
     const int lane = threadIdx.x & 63;
-    const int lo0 = d[0], lo1 = d[2], lo2 = d[4];
-    const int n0 = max(0, d[1] - lo0 + 1), n1 = max(0, d[3] - lo1 + 1), n2 = max(0, d[5] - lo2 + 1);
-    const int total = n0 + n1 + n2;
     int64_t spins = 0;
     for (int base = 0; base < total; base += 64) {
         const int i = base + lane;
-        const int j = i < n0 ? lo0 + i : i < n0 + n1 ? lo1 + (i - n0) : i < total ? lo2 + (i - n0 - n1) : -1;
+        const int j = i < total ? index(i) : -1;
         for (;;) {
             const bool ok = (j < 0) || (ld_agent(f + j) == a.epoch);
             if (__all(ok)) break;
@@ -258,10 +262,35 @@ __device__ bool wait_flags(const uint32_t *f, const int32_t *d, const MpkArgs &a
             __builtin_amdgcn_s_sleep(1);
         }
     }
+    return true;
+}
+
+// Waits for the dependencies of `tile` at the previous power (flags f):
+// the three tile ranges d[0..1], d[2..3], d[4..5] of dep3 (inclusive,
+// lo > hi = empty) or, for refined plans, the tile's range list.
+__device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ticket) {
+    bool ok;
+    if (a.dep_lists) {
+        // a list holds few ranges: each is polled on its own
+        const int k0 = a.dep_ptr[tile], k1 = a.dep_ptr[tile + 1];
+        ok = true;
+        for (int k = k0; k < k1 && ok; ++k) {
+            const int lo = a.dep_rng[2 * k], hi = a.dep_rng[2 * k + 1];
+            ok = poll_flags(f, hi - lo + 1, [=](int i) { return lo + i; }, a, ticket);
+        }
+    } else {
+        const int32_t *d = a.dep3 + 6 * tile;
+        const int lo0 = d[0], lo1 = d[2], lo2 = d[4];
+        const int n0 = max(0, d[1] - lo0 + 1), n1 = max(0, d[3] - lo1 + 1), n2 = max(0, d[5] - lo2 + 1);
+        ok = poll_flags(
+            f, n0 + n1 + n2,
+            [=](int i) { return i < n0 ? lo0 + i : i < n0 + n1 ? lo1 + (i - n0) : lo2 + (i - n0 - n1); }, a,
+            ticket);
+    }
     // Without line-closed dependencies a cache may hold a line of y_{q-1}
     // read before all its rows were final: invalidate before reading.
-    if (a.acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
+    if (ok && a.acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
 }
 
 __device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
@@ -322,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
             if (threadIdx.x == 0) s_ok = 1;
             lds_barrier();
             if (threadIdx.x < 64) {
-                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, a.dep3 + 6 * tile, a, base + t);
+                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, tile, a, base + t);
                 if (!ok && threadIdx.x == 0) s_ok = 0;
             }
             lds_barrier();
@@ -564,6 +593,8 @@ mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, cons
     }
     if (o.root_mode != plan->hp.opt.root_mode)
         return fail(MPK_ERR_ARG, "retune keeps the BFS levels: root_mode must not change");
+    if (plan->hp.recursive || o.recursion_stages != 0)
+        return fail(MPK_ERR_UNSUPPORTED, "a refined numbering depends on p and C: create a new plan");
     if (!supported(o.val_dtype, o.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
     const bool was_uploaded = plan->uploaded;
     if (was_uploaded) {
@@ -610,6 +641,23 @@ mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info) {
     for (int i = 0; i < 4; ++i) info->phase_seconds[i] = h.phase_seconds[i];
     info->line_closed_deps = h.line_closed_ok ? 1 : 0;
     info->last_run_fenced = plan->last_run_fenced;
+    info->recursive = h.recursive ? 1 : 0;
+    info->n_units = h.recursive ? (int64_t)h.unit_ptr.size() - 1 : info->n_groups;
+    info->n_dep_ranges = h.recursive ? (int64_t)h.dep_rng.size() / 2 : 0;
+    info->max_stage = 0;
+    for (int32_t st : h.unit_stage) info->max_stage = std::max(info->max_stage, st);
+    return MPK_OK;
+}
+
+mpk_status mpk_plan_units(const mpk_plan *plan, int32_t *unit_ptr, int32_t *unit_stage, int32_t *dep_ptr,
+                          int32_t *dep_rng) {
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    const HostPlan &h = plan->hp;
+    if (!h.recursive) return fail(MPK_ERR_STATE, "the plan has no refined levels (recursion_stages = 0)");
+    if (unit_ptr) std::copy(h.unit_ptr.begin(), h.unit_ptr.end(), unit_ptr);
+    if (unit_stage) std::copy(h.unit_stage.begin(), h.unit_stage.end(), unit_stage);
+    if (dep_ptr) std::copy(h.dep_ptr.begin(), h.dep_ptr.end(), dep_ptr);
+    if (dep_rng) std::copy(h.dep_rng.begin(), h.dep_rng.end(), dep_rng);
     return MPK_OK;
 }
 
@@ -686,6 +734,10 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     if ((e = dev_alloc(al, &plan->d_tile_row, T + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "tiles");
     if ((e = dev_alloc(al, &plan->d_dep3, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_dep3x, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_dep_ptr, std::max<size_t>(h.dep_ptr.size(), 1), &bytes)) != hipSuccess)
+        return cleanup_fail(e, "deps");
+    if ((e = dev_alloc(al, &plan->d_dep_rng, std::max<size_t>(h.dep_rng.size(), 2), &bytes)) != hipSuccess)
+        return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_work, W, &bytes)) != hipSuccess) return cleanup_fail(e, "work");
     if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
     if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
@@ -702,6 +754,8 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
         {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
         {plan->d_dep3x, h.dep3x.data(), sizeof(int32_t) * 6 * T},
+        {plan->d_dep_ptr, h.dep_ptr.data(), sizeof(int32_t) * h.dep_ptr.size()},
+        {plan->d_dep_rng, h.dep_rng.data(), sizeof(int32_t) * h.dep_rng.size()},
         {plan->d_work, h.work_streams.data(), sizeof(int32_t) * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
         {plan->d_chunk, desc.data(), sizeof(int32_t) * desc.size()},
@@ -788,6 +842,9 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.acquire = closed ? 0 : 1;
     plan->last_run_fenced = a.acquire;
     a.dep3 = closed ? plan->d_dep3x : plan->d_dep3;
+    a.dep_ptr = plan->d_dep_ptr;
+    a.dep_rng = plan->d_dep_rng;
+    a.dep_lists = h.recursive ? 1 : 0;
     a.work = plan->d_work;
     a.n = (int32_t)h.n;
     a.ntiles = (int32_t)h.dep_lo.size();
@@ -842,6 +899,7 @@ mpk_status mpk_run_sync(mpk_plan *plan, const double *X, double *Y, int32_t gran
     if (granularity != MPK_SYNC_NODE && granularity != MPK_SYNC_WAVEFRONT)
         return fail(MPK_ERR_ARG, "granularity must be MPK_SYNC_NODE or MPK_SYNC_WAVEFRONT");
     HostPlan &h = plan->hp;
+    if (h.recursive) return fail(MPK_ERR_UNSUPPORTED, "bulk-synchronous runs need an unrefined plan");
     if (h.n == 0) return MPK_OK;
     if (!supported(h.opt.val_dtype, h.opt.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
     const int K = h.opt.nrhs;

@@ -40,6 +40,14 @@ struct HostPlan {
     std::vector<int32_t> dep_lo, dep_hi;  // n_tiles: all tiles a tile waits for
     std::vector<int32_t> dep3;       // 6*n_tiles: (lo, hi) in groups g-1, g, g+1 (lo > hi: none)
     std::vector<int32_t> dep3x;      // the same ranges widened to whole cache lines
+    // recursive plans (Sec. 4.4): final groups ("units") of the refined
+    // numbering, and per-tile dependency lists of tile ranges
+    bool recursive = false;
+    std::vector<int32_t> unit_ptr;   // n_units+1 row boundaries
+    std::vector<int32_t> unit_stage; // n_units
+    std::vector<int64_t> unit_key;   // n_units: wavefront key of the unit's position
+    std::vector<int32_t> dep_ptr;    // n_tiles+1 into dep_rng pairs
+    std::vector<int32_t> dep_rng;    // (lo, hi) inclusive tile ranges, line-closed
     bool line_closed_ok = false;     // every widened dependency is an earlier ticket
     std::vector<int32_t> group_tile; // G+1
     std::vector<int32_t> work;       // tickets: tile*64 + (q-1)
@@ -60,6 +68,7 @@ struct ScheduleState {
     uint64_t cache_bytes;
     mpk_options opt;
     bool line_closed_ok;
+    std::vector<int32_t> dep_ptr, dep_rng;
     std::vector<int32_t> group_ptr, schedule, tile_row, tile_group, dep_lo, dep_hi, dep3, dep3x, group_tile, work,
         stream_ptr, work_streams, chunk_row, tile_chunk;
     int64_t max_group_nnz, violating_groups;

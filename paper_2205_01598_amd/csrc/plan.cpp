@@ -12,6 +12,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <tuple>
 
 #include <omp.h>
 
@@ -323,6 +324,271 @@ void bfs_levels(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &p
     }
 }
 
+// ---------------------------------------------------------------------------
+// Recursive level refinement (Sec. 4.4)
+// ---------------------------------------------------------------------------
+
+// Eq. (5) test for a set of rows: (p+1) * bytes < floor(f*C), bytes = nonzeros
+// times b_nz (plus the k vector entries per row with budget_vectors).
+struct Eq5 {
+    int64_t p, bnz, nrhs;
+    bool vectors;
+    uint64_t budget;
+    bool fits(int64_t nz, int64_t rows) const {
+        unsigned __int128 per = (unsigned __int128)nz * (uint64_t)bnz;
+        if (vectors) per += (unsigned __int128)rows * 8u * (uint64_t)nrhs;
+        return per * (uint64_t)(p + 1) < (unsigned __int128)budget;
+    }
+};
+
+// Greedy level groups of Eq. (5) over levels [lptr[l], lptr[l+1]) of `rows`.
+std::vector<int64_t> eq5_groups(const std::vector<int32_t> &rows, const std::vector<int64_t> &lptr,
+                                const int64_t *rowlen, const Eq5 &eq, std::vector<int64_t> &gnz,
+                                std::vector<int64_t> &grows) {
+    const int64_t L = (int64_t)lptr.size() - 1;
+    std::vector<int64_t> lnz(L, 0);
+    for (int64_t l = 0; l < L; ++l)
+        for (int64_t r = lptr[l]; r < lptr[l + 1]; ++r) lnz[l] += rowlen[rows[r]];
+    std::vector<int64_t> gptr{0};
+    gnz.clear();
+    grows.clear();
+    for (int64_t l = 0; l < L;) {
+        int64_t nz = lnz[l], nr = lptr[l + 1] - lptr[l], e = l + 1;
+        while (e < L && eq.fits(nz + lnz[e], nr + (lptr[e + 1] - lptr[e]))) {
+            nz += lnz[e];
+            nr += lptr[e + 1] - lptr[e];
+            ++e;
+        }
+        gptr.push_back(e);
+        gnz.push_back(nz);
+        grows.push_back(nr);
+        l = e;
+    }
+    return gptr;
+}
+
+struct Refiner {
+    const Graph &g;
+    const int64_t *rowlen;
+    const std::vector<int32_t> &pos;  // position of every vertex in the stage-0 numbering
+    Eq5 eq;
+    int stages;
+    std::vector<uint8_t> inside, seen;
+    std::vector<int32_t> order;       // final numbering, built in order
+    std::vector<int32_t> unit_rows, unit_stage;
+    std::vector<int64_t> unit_key;
+
+    // Breadth-first levels of the subgraph induced by `region` (listed in the
+    // current numbering): root = its first row; every vertex, taken in the
+    // new order, appends its unvisited neighbours inside the region in
+    // ascending position; an empty frontier restarts at the first unvisited
+    // row of the region.
+    void sub_levels(const std::vector<int32_t> &region, std::vector<int32_t> &out, std::vector<int64_t> &lptr) {
+        for (int32_t v : region) inside[v] = 1;
+        out.clear();
+        lptr.assign(1, 0);
+        size_t scan = 0;
+        std::vector<int32_t> nb;
+        while (out.size() < region.size()) {
+            while (seen[region[scan]]) ++scan;
+            size_t a = out.size();
+            out.push_back(region[scan]);
+            seen[region[scan]] = 1;
+            lptr.push_back((int64_t)out.size());
+            while (a < out.size()) {
+                const size_t b = out.size();
+                for (size_t f = a; f < b; ++f) {
+                    const int32_t u = out[f];
+                    nb.clear();
+                    for (int64_t j = g.ptr[u]; j < g.ptr[u + 1]; ++j) {
+                        const int32_t v = g.adj[j];
+                        if (inside[v] && !seen[v]) nb.push_back(v);
+                    }
+                    std::sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return pos[x] < pos[y]; });
+                    for (int32_t v : nb) {
+                        seen[v] = 1;
+                        out.push_back(v);
+                    }
+                }
+                if (out.size() > b) lptr.push_back((int64_t)out.size());
+                a = b;
+            }
+        }
+        for (int32_t v : region) inside[v] = 0, seen[v] = 0;
+    }
+
+    // levels [lptr] of `rows` at stage `stage`, occupying the wavefront key
+    // range [key_lo, key_hi): group i gets [key_lo + (key_hi-key_lo) i / G, ...)
+    void refine(const std::vector<int32_t> &rows, const std::vector<int64_t> &lptr, int stage, int64_t key_lo,
+                int64_t key_hi) {
+        std::vector<int64_t> gnz, grows;
+        const std::vector<int64_t> gptr = eq5_groups(rows, lptr, rowlen, eq, gnz, grows);
+        const int64_t G = (int64_t)gptr.size() - 1;
+        auto key_at = [&](int64_t i) {
+            return key_lo + (int64_t)(((__int128)(key_hi - key_lo) * i) / std::max<int64_t>(G, 1));
+        };
+        for (int64_t i = 0; i < G;) {
+            if (stage >= stages || eq.fits(gnz[i], grows[i])) {
+                for (int64_t r = lptr[gptr[i]]; r < lptr[gptr[i + 1]]; ++r) order.push_back(rows[r]);
+                unit_rows.push_back((int32_t)(lptr[gptr[i + 1]] - lptr[gptr[i]]));
+                unit_stage.push_back(stage);
+                unit_key.push_back(key_at(i));
+                ++i;
+                continue;
+            }
+            int64_t j = i;
+            while (j < G && !eq.fits(gnz[j], grows[j])) ++j;
+            std::vector<int32_t> region(rows.begin() + lptr[gptr[i]], rows.begin() + lptr[gptr[j]]);
+            std::vector<int32_t> sub;
+            std::vector<int64_t> sub_lptr;
+            sub_levels(region, sub, sub_lptr);
+            refine(sub, sub_lptr, stage + 1, key_at(i), key_at(j));
+            i = j;
+        }
+    }
+};
+
+constexpr int64_t kKeyUnit = 1 << 24;  // wavefront key of one stage-0 level group
+
+// Schedule of a refined plan: tiles inside the final groups ("units"),
+// per-tile dependency lists (every tile holding a column the tile reads, and
+// the tile itself, widened to whole 128-byte lines of an aligned N x k FP64
+// slice), and tickets ordered by a longest-path wavefront number of the
+// (unit, power) nodes
+//   wf(u, 1) = key(u),  wf(u, q) = max(key(u) + skew*K*(q-1), max_v wf(v, q-1) + 1)
+// over the units v holding a dependency of a tile of u, K = kKeyUnit, then
+// by power and tile.  Every dependency has a smaller wavefront number (or is
+// the node's own earlier power), so the order is topological; for unrefined
+// groups (key g*K) it is the order of the diagonal g + skew*q.
+mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &opt) {
+    const int64_t n = hp.n;
+    if (opt.xcd_streams != 1) return fail(MPK_ERR_UNSUPPORTED, "a refined plan uses one ticket stream");
+    int64_t tile_nnz = opt.tile_nnz > 0 ? opt.tile_nnz : 8192;
+    const int64_t max_tile_rows = 1 << 14;
+    hp.tile_nnz = (int32_t)tile_nnz;
+    hp.tile_row.clear();
+    hp.tile_group.clear();
+    hp.group_tile.clear();
+    const int64_t U = (int64_t)hp.unit_ptr.size() - 1;
+    for (int64_t u = 0; u < U; ++u) {
+        hp.group_tile.push_back((int32_t)hp.tile_group.size());
+        const int64_t r0 = hp.unit_ptr[u], r1 = hp.unit_ptr[u + 1];
+        const int64_t gnz = hp.rowptr[r1] - hp.rowptr[r0];
+        int64_t nt = std::max<int64_t>(1, (gnz + tile_nnz - 1) / tile_nnz);
+        nt = std::min<int64_t>(nt, r1 - r0);
+        std::vector<int64_t> bnd{r0};
+        for (int64_t t = 1; t < nt; ++t) {
+            const int64_t target = hp.rowptr[r0] + (gnz * t) / nt;
+            const int64_t lo = bnd.back() + 1, hi = r1 - (nt - t);
+            const int64_t a = std::lower_bound(hp.rowptr.begin() + lo, hp.rowptr.begin() + hi + 1, (int32_t)target) -
+                              hp.rowptr.begin();
+            bnd.push_back(std::min<int64_t>(std::max<int64_t>(a, lo), hi));
+        }
+        bnd.push_back(r1);
+        for (size_t t = 0; t + 1 < bnd.size(); ++t)
+            for (int64_t r = bnd[t]; r < bnd[t + 1]; r += max_tile_rows) {
+                hp.tile_row.push_back((int32_t)r);
+                hp.tile_group.push_back((int32_t)u);
+            }
+    }
+    hp.group_tile.push_back((int32_t)hp.tile_group.size());
+    hp.tile_row.push_back((int32_t)n);
+    const int64_t T = (int64_t)hp.tile_group.size();
+
+    // dependency lists
+    std::vector<int32_t> row_tile(n);
+    for (int64_t t = 0; t < T; ++t)
+        for (int64_t r = hp.tile_row[t]; r < hp.tile_row[t + 1]; ++r) row_tile[r] = (int32_t)t;
+    const int64_t Rl = std::max<int64_t>(1, 128 / (8 * (int64_t)opt.nrhs));
+    std::vector<std::vector<int32_t>> ranges(T);
+#pragma omp parallel
+    {
+        std::vector<int32_t> ts;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < T; ++t) {
+            ts.clear();
+            ts.push_back((int32_t)t);
+            for (int64_t j = hp.rowptr[hp.tile_row[t]]; j < hp.rowptr[hp.tile_row[t + 1]]; ++j)
+                ts.push_back(row_tile[hp.col[j]]);
+            std::sort(ts.begin(), ts.end());
+            ts.erase(std::unique(ts.begin(), ts.end()), ts.end());
+            std::vector<int32_t> &out = ranges[t];
+            for (size_t a = 0; a < ts.size();) {
+                size_t b = a;
+                while (b + 1 < ts.size() && ts[b + 1] == ts[b] + 1) ++b;
+                const int64_t f = hp.tile_row[ts[a]], l = hp.tile_row[ts[b] + 1] - 1;
+                const int64_t f2 = f - f % Rl, l2 = std::min<int64_t>(n - 1, l + (Rl - 1 - l % Rl));
+                const int32_t lo = row_tile[f2], hi = row_tile[l2];
+                if (!out.empty() && lo <= out.back() + 1)
+                    out.back() = std::max(out.back(), hi);
+                else {
+                    out.push_back(lo);
+                    out.push_back(hi);
+                }
+                a = b + 1;
+            }
+        }
+    }
+    hp.dep_ptr.assign(T + 1, 0);
+    for (int64_t t = 0; t < T; ++t) hp.dep_ptr[t + 1] = hp.dep_ptr[t] + (int32_t)(ranges[t].size() / 2);
+    hp.dep_rng.resize(2 * (size_t)hp.dep_ptr[T]);
+    hp.dep_lo.assign(T, 0);
+    hp.dep_hi.assign(T, 0);
+    for (int64_t t = 0; t < T; ++t) {
+        std::copy(ranges[t].begin(), ranges[t].end(), hp.dep_rng.begin() + 2 * (size_t)hp.dep_ptr[t]);
+        hp.dep_lo[t] = ranges[t].front();
+        hp.dep_hi[t] = ranges[t].back();
+    }
+    // the three-range tables of unrefined plans: empty here
+    hp.dep3.assign(6 * T, 0);
+    for (int64_t t = 0; t < T; ++t)
+        for (int m = 0; m < 3; ++m) hp.dep3[6 * t + 2 * m] = 1;
+    hp.dep3x = hp.dep3;
+    hp.line_closed_ok = true;
+
+    // kernel chunks inside every tile
+    hp.chunk_row.clear();
+    hp.tile_chunk.assign(T + 1, 0);
+    const int64_t cnz = chunk_nnz_host(opt.nrhs);
+    for (int64_t t = 0; t < T; ++t) {
+        hp.tile_chunk[t] = (int32_t)hp.chunk_row.size();
+        append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, kChunkRows, hp.chunk_row);
+    }
+    hp.tile_chunk[T] = (int32_t)hp.chunk_row.size();
+    hp.chunk_row.push_back((int32_t)n);
+
+    // wavefront numbers per (unit, power) node, so the tiles of a node stay
+    // contiguous in row order as in the unrefined ticket order
+    const int64_t S = (int64_t)opt.skew * kKeyUnit;
+    std::vector<int64_t> wf(U), wf_next(U);
+    for (int64_t u = 0; u < U; ++u) wf[u] = hp.unit_key[u];
+    std::vector<std::tuple<int64_t, int32_t, int32_t>> tk;
+    tk.reserve((size_t)T * p);
+    for (int64_t t = 0; t < T; ++t) tk.emplace_back(wf[hp.tile_group[t]], 1, (int32_t)t);
+    for (int32_t q = 2; q <= p; ++q) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t u = 0; u < U; ++u) {
+            int64_t w = hp.unit_key[u] + S * (q - 1);
+            for (int32_t t = hp.group_tile[u]; t < hp.group_tile[u + 1]; ++t)
+                for (int32_t k = hp.dep_ptr[t]; k < hp.dep_ptr[t + 1]; ++k) {
+                    const int32_t g0 = hp.tile_group[hp.dep_rng[2 * k]], g1 = hp.tile_group[hp.dep_rng[2 * k + 1]];
+                    for (int32_t g = g0; g <= g1; ++g) w = std::max(w, wf[g] + 1);
+                }
+            wf_next[u] = w;
+        }
+        wf.swap(wf_next);
+        for (int64_t t = 0; t < T; ++t) tk.emplace_back(wf[hp.tile_group[t]], q, (int32_t)t);
+    }
+    std::sort(tk.begin(), tk.end());
+    hp.work.clear();
+    hp.work.reserve(tk.size());
+    for (const auto &x : tk) hp.work.push_back(std::get<2>(x) * 64 + (std::get<1>(x) - 1));
+    hp.stream_ptr.assign(2, 0);
+    hp.stream_ptr[1] = (int32_t)hp.work.size();
+    hp.work_streams = hp.work;
+    return MPK_OK;
+}
+
 }  // namespace
 
 mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const mpk_options &opt) {
@@ -385,6 +651,8 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
                 hp.schedule.push_back((int32_t)(d - q));
             }
         }
+
+        if (hp.recursive) return build_recursive_schedule(hp, p, opt);
 
         // ---- device tiles --------------------------------------------------------------
         int64_t tile_nnz = opt.tile_nnz;
@@ -578,6 +846,8 @@ void save_schedule(HostPlan &hp, ScheduleState &s) {
     s.dep3 = hp.dep3;
     s.dep3x = hp.dep3x;
     s.line_closed_ok = hp.line_closed_ok;
+    s.dep_ptr = hp.dep_ptr;
+    s.dep_rng = hp.dep_rng;
     s.group_tile = hp.group_tile;
     s.work = hp.work;
     s.stream_ptr = hp.stream_ptr;
@@ -602,6 +872,8 @@ void restore_schedule(HostPlan &hp, ScheduleState &s) {
     hp.dep3.swap(s.dep3);
     hp.dep3x.swap(s.dep3x);
     hp.line_closed_ok = s.line_closed_ok;
+    hp.dep_ptr.swap(s.dep_ptr);
+    hp.dep_rng.swap(s.dep_rng);
     hp.group_tile.swap(s.group_tile);
     hp.work.swap(s.work);
     hp.stream_ptr.swap(s.stream_ptr);
@@ -658,6 +930,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
     if (opt.plan_on_device != 0 && opt.plan_on_device != 1) return fail(MPK_ERR_ARG, "plan_on_device must be 0 or 1");
     if (opt.force_acquire != 0 && opt.force_acquire != 1) return fail(MPK_ERR_ARG, "force_acquire must be 0 or 1");
+    if (opt.recursion_stages < 0 || opt.recursion_stages > 16) return fail(MPK_ERR_ARG, "recursion_stages must be in [0, 16]");
 
     const int64_t n = A->n;
     hp.n = n;
@@ -674,7 +947,8 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
         // On the GPU: graph, levels and P A P^T for a sorted symmetric pattern;
         // otherwise the host builds the graph (and, on the GPU, only the levels).
         bool on_device = false;
-        if (opt.plan_on_device) {
+        std::vector<int32_t> perm0;  // stage-0 numbering of a refined plan (its levels)
+        if (opt.plan_on_device && opt.recursion_stages == 0) {
             st = device_plan(A, opt.root_mode, &hp.root, hp.perm, hp.level_ptr, hp.rowptr, hp.col, hp.val, &on_device,
                              hp.phase_seconds);
             if (st != MPK_OK) return st;
@@ -691,6 +965,29 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                 if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
                 bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
             }
+            if (opt.recursion_stages > 0 && n > 0) {
+                // Sec. 4.4: refine maximal runs of groups that violate Eq. (5)
+                std::vector<int64_t> rowlen(n);
+                for (int64_t i = 0; i < n; ++i) rowlen[i] = A->rowptr[i + 1] - A->rowptr[i];
+                std::vector<int32_t> pos(n);
+                for (int64_t i = 0; i < n; ++i) pos[hp.perm[i]] = (int32_t)i;
+                Eq5 eq{p, bytes_per_nnz(opt.val_dtype), opt.nrhs, opt.budget_vectors != 0,
+                       (uint64_t)std::floor(opt.safety_factor * (double)cache_bytes)};
+                std::vector<int64_t> lp64(hp.level_ptr.begin(), hp.level_ptr.end());
+                std::vector<int64_t> gnz, grows;
+                const int64_t G0 = (int64_t)eq5_groups(hp.perm, lp64, rowlen.data(), eq, gnz, grows).size() - 1;
+                Refiner rf{g, rowlen.data(), pos, eq, opt.recursion_stages, std::vector<uint8_t>(n, 0),
+                           std::vector<uint8_t>(n, 0), {}, {}, {}, {}};
+                rf.order.reserve(n);
+                rf.refine(hp.perm, lp64, 0, 0, G0 * kKeyUnit);
+                perm0.swap(hp.perm);
+                hp.perm.swap(rf.order);
+                hp.unit_ptr.assign(rf.unit_rows.size() + 1, 0);
+                for (size_t u = 0; u < rf.unit_rows.size(); ++u) hp.unit_ptr[u + 1] = hp.unit_ptr[u] + rf.unit_rows[u];
+                hp.unit_stage = rf.unit_stage;
+                hp.unit_key = rf.unit_key;
+                hp.recursive = true;
+            }
             hp.phase_seconds[0] = secs(ta, tb);
             hp.phase_seconds[1] = secs(tb, now());
         }
@@ -704,7 +1001,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
         for (int64_t l = 0; l < L; ++l) {
             int64_t s = 0;
             for (int64_t r = hp.level_ptr[l]; r < hp.level_ptr[l + 1]; ++r) {
-                int64_t o = hp.perm[r];
+                int64_t o = hp.recursive ? perm0[r] : hp.perm[r];
                 s += A->rowptr[o + 1] - A->rowptr[o];
             }
             hp.level_nnz[l] = s;

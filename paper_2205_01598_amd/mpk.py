@@ -146,6 +146,19 @@ class Plan:
         check(lib().mpk_plan_tile_deps(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(line_closed)))
         return d.reshape(T, 6)
 
+    def units(self):
+        """Refined plans (recursion_stages > 0, Sec. 4.4): (unit_ptr,
+        unit_stage, dep_ptr, dep_rng) as numpy arrays; dep_rng has shape
+        (n_dep_ranges, 2), inclusive tile ranges."""
+        info = self.info()
+        U, T, R = info["n_units"], info["n_tiles"], info["n_dep_ranges"]
+        up, us = np.empty(U + 1, np.int32), np.empty(U, np.int32)
+        dp, dr = np.empty(T + 1, np.int32), np.empty(2 * R, np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        check(lib().mpk_plan_units(self._h, up.ctypes.data_as(P), us.ctypes.data_as(P), dp.ctypes.data_as(P),
+                                   dr.ctypes.data_as(P)))
+        return up, us, dp, dr.reshape(R, 2)
+
     # -- device calls ------------------------------------------------------------
     def permute(self, x, out, to_plan: bool, stream=None):
         k = 1 if x.dim() == 1 else x.shape[-1]
