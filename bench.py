@@ -92,6 +92,35 @@ def spmv_bytes(n, nnz, k=1, vbytes=8):
     return (vbytes + 4) * nnz + 4 * (n + 1) + 16 * n * k
 
 
+def timed_each(torch, fn, min_seconds=1.0, max_runs=2000, before=None):
+    """Times single calls with events until at least `min_seconds` of GPU
+    time has been measured; `before` (untimed) runs ahead of every call.
+    Returns (mean, min, median) in ms and the number of calls."""
+    ts = []
+    while sum(ts) < min_seconds * 1e3 and len(ts) < max_runs:
+        if before is not None:
+            before()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e))
+    return float(np.mean(ts)), float(np.min(ts)), float(np.median(ts)), len(ts)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def rel_errs(Y, ref):
     return [float(np.linalg.norm(Y[q] - ref[q]) / np.linalg.norm(ref[q])) for q in range(ref.shape[0])]
 
@@ -138,6 +167,17 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
         pl.status()
         ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
                "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1)}
+        if dt == "f64":
+            # the working set fits the 256 MB Infinity Cache: also time each
+            # step after reading 512 MB of other data
+            scrub = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+            sink = torch.empty((), dtype=torch.float64, device=dev)
+            wipe = lambda: sink.copy_(scrub.sum())  # noqa: E731
+            sm = timed_each(torch, lambda: prop.step(X, acc), 0.1, 40, before=wipe)[0]
+            sb = timed_each(torch, lambda: prop.step(X, acc, baseline=True), 0.1, 40, before=wipe)[0]
+            ent["cache_scrubbed"] = {"step_ms": round(sm, 4), "baseline_step_ms": round(sb, 4),
+                                     "speedup": round(sb / sm, 3)}
+            del scrub, sink
         states, state = [], X
         for _ in range(steps_err):
             nxt = torch.empty_like(state)
@@ -264,12 +304,15 @@ def cpu_baseline_leg(A, x, p, flop):
     input; its output also gives the FP64 error of the GPU result."""
     import oracle as O
 
-    t0 = time.time()
-    ref = O.spmv_powers(A, x, p)
-    cpu_s = time.time() - t0
+    runs = []
+    while sum(runs) < 10.0 and len(runs) < 8:
+        t0 = time.time()
+        ref = O.spmv_powers(A, x, p)
+        runs.append(time.time() - t0)
+    cpu_s = float(np.mean(runs))
     cpu = {"value": round(flop / cpu_s / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-           "sample": f"one full FP64 p={p} run (p back-to-back CSR SpMVs) of the same 160^3 matrix, "
-                     f"{cpu_s:.1f} s on one host thread"}
+           "sample": f"{len(runs)} full FP64 p={p} runs (p back-to-back CSR SpMVs) of the same 160^3 matrix, "
+                     f"mean {cpu_s:.2f} s (min {min(runs):.2f} s) on one host thread of {cpu_model()}"}
     return cpu, ref
 
 
@@ -372,6 +415,10 @@ def main():
     Yh[:, perm] = Y.cpu().numpy()
     gflops = flop / ms / 1e6
     alg_bytes = mpk_bytes(n, nnz, p)
+    # per-call statistics over at least one second of single timed calls
+    t_mean, t_min, t_med, t_n = timed_each(torch, lambda: plan.run(X, Y))
+    plan.status()
+    per_call = {"calls": t_n, "mean_ms": round(t_mean, 4), "min_ms": round(t_min, 4), "median_ms": round(t_med, 4)}
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"MPK p={p}: {ms:.3f} ms/step, {gflops:.1f} GFLOP/s, speedup {t_base / ms:.3f}")
 
@@ -483,6 +530,7 @@ def main():
                    "workgroups": info["workgroups"], "levels": info["n_levels"],
                    "level_groups": info["n_groups"], "seed": args.seed},
         "speedup_vs_spmv": round(t_base / ms, 3),
+        "per_call_timing": per_call,
         "baseline_ms": {k: round(v, 4) for k, v in base.items()},
         "baseline_gflops": round(flop / t_base / 1e6, 1),
         "plan_seconds": round(plan_s, 2),

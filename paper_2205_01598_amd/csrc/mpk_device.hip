@@ -45,7 +45,6 @@ struct mpk_plan {
     int device = -1;
     int32_t workgroups = 0;
     int32_t num_cus = 0;
-    uint32_t epoch = 0;
     int32_t last_run_fenced = -1;
     uint64_t device_bytes = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr;
@@ -70,7 +69,8 @@ struct mpk_spmv {
 
 namespace {
 
-// control words: [1] departures, [2] epoch of a timed-out run, [3] ticket
+// control words: [0] epoch of the last run (written by its last workgroup),
+// [1] departures, [2] epoch of a timed-out run, [3] ticket
 // that timed out, [16..23] arrivals per stream, then one ticket counter per
 // (stream, sub-stripe) pair, 256 B apart
 constexpr int kMaxStripes = 64;
@@ -217,7 +217,6 @@ struct MpkArgs {
     double *Y;
     uint32_t *flags;
     uint32_t *ctrl;
-    uint32_t epoch;
     int32_t nstreams;
     int32_t stream_ptr[kMaxStreams + 1];
     int64_t watchdog;
@@ -241,24 +240,25 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 // load.  Returns false if the watchdog expired (and reports the ticket) or
 // another workgroup already reported a timeout in this run.
 template <typename Index>
-__device__ bool poll_flags(const uint32_t *f, int total, Index index, const MpkArgs &a, int ticket) {
+__device__ bool poll_flags(const uint32_t *f, int total, Index index, const MpkArgs &a, int ticket,
+                           uint32_t epoch) {
     const int lane = threadIdx.x & 63;
     int64_t spins = 0;
     for (int base = 0; base < total; base += 64) {
         const int i = base + lane;
         const int j = i < total ? index(i) : -1;
         for (;;) {
-            const bool ok = (j < 0) || (ld_agent(f + j) == a.epoch);
+            const bool ok = (j < 0) || (ld_agent(f + j) == epoch);
             if (__all(ok)) break;
             ++spins;
             if (spins > a.watchdog) {
                 if (lane == 0) {
                     st_agent(a.ctrl + 3, (uint32_t)ticket);
-                    st_agent(a.ctrl + 2, a.epoch);
+                    st_agent(a.ctrl + 2, epoch);
                 }
                 return false;
             }
-            if ((spins & 255) == 0 && ld_agent(a.ctrl + 2) == a.epoch) return false;
+            if ((spins & 255) == 0 && ld_agent(a.ctrl + 2) == epoch) return false;
             __builtin_amdgcn_s_sleep(1);
         }
     }
@@ -268,7 +268,7 @@ __device__ bool poll_flags(const uint32_t *f, int total, Index index, const MpkA
 // Waits for the dependencies of `tile` at the previous power (flags f):
 // the three tile ranges d[0..1], d[2..3], d[4..5] of dep3 (inclusive,
 // lo > hi = empty) or, for refined plans, the tile's range list.
-__device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ticket) {
+__device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ticket, uint32_t epoch) {
     bool ok;
     if (a.dep_lists) {
         // a list holds few ranges: each is polled on its own
@@ -276,7 +276,7 @@ __device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ti
         ok = true;
         for (int k = k0; k < k1 && ok; ++k) {
             const int lo = a.dep_rng[2 * k], hi = a.dep_rng[2 * k + 1];
-            ok = poll_flags(f, hi - lo + 1, [=](int i) { return lo + i; }, a, ticket);
+            ok = poll_flags(f, hi - lo + 1, [=](int i) { return lo + i; }, a, ticket, epoch);
         }
     } else {
         const int32_t *d = a.dep3 + 6 * tile;
@@ -285,7 +285,7 @@ __device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ti
         ok = poll_flags(
             f, n0 + n1 + n2,
             [=](int i) { return i < n0 ? lo0 + i : i < n0 + n1 ? lo1 + (i - n0) : lo2 + (i - n0 - n1); }, a,
-            ticket);
+            ticket, epoch);
     }
     // Without line-closed dependencies a cache may hold a line of y_{q-1}
     // read before all its rows were final: invalidate before reading.
@@ -310,6 +310,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     // next for, a running workgroup whose earlier tickets are done: the grid
     // needs no co-residency.  The last workgroup to leave resets the counters.
     __shared__ int s_sub, s_ok;
+    __shared__ uint32_t s_epoch;
     __shared__ int s_next[2];
     __shared__ ChunkLds<VT, K> lds;
     const int nS = a.nstreams;
@@ -328,8 +329,16 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_sub = sub;
         s_next[0] = (int)min<int64_t>((int64_t)sub + (int64_t)k * S, len);
+        // The run's epoch: one past the last run's (control word 0, written
+        // by the last workgroup of that run, so every workgroup of this run
+        // reads the same value); the flags of earlier runs never match it.
+        // The launch arguments do not change between runs, so a captured
+        // launch can be replayed.
+        uint32_t e = ld_agent(a.ctrl) + 1u;
+        s_epoch = e == 0u ? 1u : e;
     }
     __syncthreads();
+    const uint32_t epoch = s_epoch;
     const int counter = stream * (kMaxStripes / nS) + s_sub;
     const int sub = s_sub;
     int t = s_next[0];
@@ -351,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
             if (threadIdx.x == 0) s_ok = 1;
             lds_barrier();
             if (threadIdx.x < 64) {
-                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, tile, a, base + t);
+                const bool ok = wait_flags(a.flags + (int64_t)(q - 2) * a.ntiles, tile, a, base + t, epoch);
                 if (!ok && threadIdx.x == 0) s_ok = 0;
             }
             lds_barrier();
@@ -377,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         if (threadIdx.x == 0) s_next[it & 1] = (int)min<int64_t>((int64_t)sub + (int64_t)kn * S, len);
         __syncthreads();
-        if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, a.epoch);
+        if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, epoch);
         t = s_next[it & 1];
     }
     if (threadIdx.x == 0) {
@@ -386,6 +395,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
             for (int st = 0; st < kMaxStripes; ++st) st_agent(stripe_counter(a, st), 0u);
             for (int st = 0; st < kMaxStreams; ++st) st_agent(a.ctrl + kArrivalBase + st, 0u);
             st_agent(a.ctrl + 1, 0u);
+            st_agent(a.ctrl, epoch);
         }
     }
 }
@@ -611,7 +621,6 @@ mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, cons
         if (was_uploaded) (void)mpk_plan_upload(plan);
         return st;
     }
-    plan->epoch = 0;
     if (was_uploaded) return mpk_plan_upload(plan);
     return MPK_OK;
 }
@@ -826,8 +835,6 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
-    plan->epoch += 1;
-    if (plan->epoch == 0) plan->epoch = 1;
     MpkArgs a;
     a.chunk = reinterpret_cast<const int4 *>(plan->d_chunk);
     a.tile_chunk = plan->d_tile_chunk;
@@ -855,7 +862,6 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.Y = Y;
     a.flags = plan->d_flags;
     a.ctrl = plan->d_ctrl;
-    a.epoch = plan->epoch;
     a.watchdog = h.opt.watchdog_spins > 0 ? h.opt.watchdog_spins : (int64_t)1 << 24;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.nrhs, rec != nullptr, [&](auto d) {
@@ -956,7 +962,8 @@ mpk_status mpk_plan_status(mpk_plan *plan, void *stream) {
     HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
     uint32_t ctrl[4];
     HIP_TRY(hipMemcpy(ctrl, plan->d_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost));
-    if (plan->epoch != 0 && ctrl[2] == plan->epoch)
+    // ctrl[0]: epoch of the last completed run; ctrl[2]: epoch of a run that timed out
+    if (ctrl[0] != 0 && ctrl[2] == ctrl[0])
         return fail(MPK_ERR_TIMEOUT, "dependency wait timed out at ticket " + std::to_string(ctrl[3]));
     return MPK_OK;
 }
