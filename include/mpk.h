@@ -231,7 +231,9 @@ mpk_status mpk_plan_tiles(const mpk_plan *plan, int32_t *tile_row, int32_t *dep_
  * limiting the reads of a group to its two neighbour groups).
  * line_closed = 1 returns the same ranges widened to whole 128-byte lines of
  * a vector slice (they may reach one tile into groups g-2 and g+2), which
- * mpk_run uses when it skips the acquire fence. */
+ * mpk_run uses when it skips the acquire fence.  A refined plan
+ * (recursion_stages > 0) keeps its dependencies in per-tile lists
+ * (mpk_plan_units); its ranges here are all empty (lo = 1 > hi = 0). */
 mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges, int32_t line_closed);
 
 /* Refined plans only (recursion_stages > 0, Sec. 4.4), host copies; any

@@ -149,3 +149,24 @@ def test_empty_and_tiny_refined():
     A = W.stencil_2d(1, 5)
     pl = Plan(A, 2, 100, upload=False, recursion_stages=1)
     assert pl.info()["n"] == 1
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_refined_plan_random_graphs(seed):
+    # small irregular matrices (unsymmetric patterns, empty rows, duplicates,
+    # disconnected parts) with random p, budget and stage limit
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(20, 700))
+    A = W.random_small_csr(n, float(rng.uniform(1.5, 8.0)) / n, rng, symmetric_pattern=bool(seed % 2),
+                           empty_rows=0.05 * (seed % 3), duplicates=0.05 * (seed % 2))
+    p = int(rng.integers(1, 9))
+    C = int(rng.integers(200, 20000))
+    stages = int(rng.integers(1, 4))
+    root_mode = seed % 2
+    pl = Plan(A, p, C, upload=False, root_mode=root_mode, recursion_stages=stages,
+              tile_nnz=int(rng.integers(8, 200)), skew=int(rng.integers(1, 3)))
+    perm, up, us = _check_refined(pl, A, p)
+    operm, olp = O.bfs_levels(A, root_mode)
+    fp, oup, ous = O.refine_levels(A, operm, olp, p, C, stages=stages)
+    assert np.array_equal(perm, fp)
+    assert np.array_equal(up, oup) and np.array_equal(us, ous)
