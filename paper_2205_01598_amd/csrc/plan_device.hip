@@ -77,7 +77,7 @@ __global__ void count(const int64_t *__restrict__ ptr, const int32_t *__restrict
     __syncthreads();
     // inclusive Hillis-Steele scan over the workgroup
     for (int d = 1; d < kThreads; d <<= 1) {
-        const int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
@@ -97,7 +97,7 @@ __global__ void scan_blocks(int32_t *blocksum, int64_t nb, int32_t *total) {
         s[threadIdx.x] = v;
         __syncthreads();
         for (int d = 1; d < kThreads; d <<= 1) {
-            const int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
             __syncthreads();
             s[threadIdx.x] += t;
             __syncthreads();
@@ -386,7 +386,7 @@ __global__ void scan_local(const int64_t *__restrict__ in, int64_t n, int64_t *_
     s[threadIdx.x] = v;
     __syncthreads();
     for (int d = 1; d < kThreads; d <<= 1) {
-        const int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        const int64_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
@@ -404,7 +404,7 @@ __global__ void scan_sums(int64_t *bsum, int64_t nb) {  // one workgroup; bsum[n
         s[threadIdx.x] = v;
         __syncthreads();
         for (int d = 1; d < kThreads; d <<= 1) {
-            const int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            const int64_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
             __syncthreads();
             s[threadIdx.x] += t;
             __syncthreads();
