@@ -145,7 +145,7 @@ def bench_small_2d(torch, Plan, W, dev):
             "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3), "sync_ladder": ladder}
 
 
-def bench_chebyshev(torch, Plan, W, dev, steps_err=2):
+def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
     """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8.
     Low-precision errors are measured against the FP64 run of the same
     steps (whose agreement with the oracle the tests establish)."""

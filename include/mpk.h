@@ -105,7 +105,7 @@ typedef struct mpk_options {
                                  0 (default): no refinement.  A refined plan orders its tickets by
                                  a longest-path wavefront number over per-tile dependency lists and
                                  cannot be retuned (the numbering depends on p and C). */
-    int32_t reserved[2];
+    int32_t reserved[2];      /* must be 0 */
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */
