@@ -162,11 +162,22 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
         prop = ChebPropagator.schroedinger(pl, M, r_dt)
         X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
         acc = torch.empty_like(X)
-        tm = timed(torch, lambda: prop.step(X, acc), 20, 3)
         tb = timed(torch, lambda: prop.step(X, acc, baseline=True), 20, 3)
+        # a small sweep of (C MB, tile nonzeros, skew); the matrix fits the
+        # Infinity Cache, so smaller budgets than the headline's are tried
+        best = None
+        for C, tile, skew in ((256, 8192, 2), (128, 4096, 2), (256, 4096, 1), (64, 2048, 2)):
+            pl.retune(p, C << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=skew, tile_nnz=tile)
+            t = timed(torch, lambda: prop.step(X, acc), 10, 2)
+            if best is None or t < best[0]:
+                best = (t, (C, tile, skew))
+        C, tile, skew = best[1]
+        pl.retune(p, C << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=skew, tile_nnz=tile)
+        tm = timed(torch, lambda: prop.step(X, acc), 20, 3)
         pl.status()
         ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
-               "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1)}
+               "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1),
+               "config": {"cache_mb": C, "tile_nnz": tile, "skew": skew}}
         if dt == "f64":
             # the working set fits the 256 MB Infinity Cache: also time each
             # step after reading 512 MB of other data
@@ -487,11 +498,22 @@ def main():
         for dt in ("f32", "bf16"):
             pm = Plan(A, p, cfg["cache"] << 20, root_mode=1, val_dtype=dt, skew=cfg["skew"],
                       tile_nnz=cfg["tile"])
+            tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
+            # the same small sweep as for FP64 (smaller values shift the best tile)
+            mbest = None
+            for c in cands + ([] if args.quick else [dict(skew=2, cache=256, tile=12288),
+                                                     dict(skew=2, cache=256, tile=16384)]):
+                pm.retune(p, c["cache"] << 20, root_mode=1, val_dtype=dt, skew=c["skew"], tile_nnz=c["tile"])
+                t = timed(torch, lambda: pm.run(X, Y), 5, 2)
+                if mbest is None or t < mbest[0]:
+                    mbest = (t, c)
+            pm.retune(p, mbest[1]["cache"] << 20, root_mode=1, val_dtype=dt, skew=mbest[1]["skew"],
+                      tile_nnz=mbest[1]["tile"])
             tm = timed(torch, lambda: pm.run(X, Y), 10, 3)
             pm.status()
-            tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
             ent = {"ms": round(tm, 4), "gflops": round(flop / tm / 1e6, 1), "baseline_ms": round(tbm, 4),
-                   "speedup_vs_fp64_baseline": round(t_base / tm, 3)}
+                   "speedup": round(tbm / tm, 3), "speedup_vs_fp64_baseline": round(t_base / tm, 3),
+                   "config": mbest[1]}
             Ym = np.empty((p, n))
             Ym[:, perm] = Y.cpu().numpy()
             ent["rel_err_vs_fp64_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, Yh)]
