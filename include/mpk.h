@@ -275,7 +275,11 @@ mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int3
  * N x k, read only) holds y_0; Y (device, p x N x k) receives y_1..y_p.  Y
  * must not overlap X, y_prev or acc.  rec = NULL gives plain powers.
  * k is the plan's nrhs.  Asynchronous; a dependency wait that outlives the
- * watchdog makes the kernel stop early and is reported by mpk_plan_status. */
+ * watchdog makes the kernel stop early and is reported by mpk_plan_status.
+ * Runs of one plan must not overlap (its flags and counters are shared).
+ * The kernel takes its run number from the plan's device memory, so the
+ * launch is the same for every run and may be recorded by stream capture
+ * and replayed; mpk_run itself allocates nothing and issues no memset. */
 mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec,
                    void *stream);
 
