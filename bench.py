@@ -463,6 +463,33 @@ def main():
                                       round(ri["n_dep_ranges"] / ri["n_tiles"], 2), "plan_seconds": round(ps, 2),
                                       "max_rel_diff_vs_unrefined": float(f"{max(rel_errs(Yr, Yh)):.3e}")}
             del pr, Xr
+        # bulky levels: the same matrix from an interior root (vertex 0 of the
+        # random relabelling), and a power-law graph whose BFS levels are few
+        # and fat (Zipf row lengths, exponent 2, uniform columns)
+        for name, Aw, rm, pw in (("27pt160_interior_root", A, 0, p),
+                                 ("zipf_4M_s2", W.zipf_rows(4_000_000, 2.0, seed=1), 1, 6)):
+            xw = W.uniform_vector(Aw.n, seed=0)
+            ent, ref_w = {}, None
+            for sm in (0, 1):
+                pw_plan = Plan(Aw, pw, 256 << 20, root_mode=rm, skew=2, tile_nnz=8192, recursion_stages=sm)
+                wperm = pw_plan.arrays()[0].astype(np.int64)
+                Xw = torch.from_numpy(np.ascontiguousarray(xw[wperm])).to(dev)
+                Yw = torch.empty((pw, Aw.n), dtype=torch.float64, device=dev)
+                if sm == 0:
+                    ent["baseline_ms"] = round(timed(torch, lambda: pw_plan.run_baseline(Xw, Yw), 5, 2), 4)
+                tw = timed(torch, lambda: pw_plan.run(Xw, Yw), 10, 2)
+                pw_plan.status()
+                Yr = np.empty((pw, Aw.n))
+                Yr[:, wperm] = Yw.cpu().numpy()
+                if ref_w is None:
+                    ref_w = Yr
+                wi = pw_plan.info()
+                ent[f"s_m={sm}"] = {"ms": round(tw, 4), "level_groups": wi["n_groups"],
+                                    "violating_groups": wi["violating_groups"], "units": wi["n_units"],
+                                    "max_rel_diff_vs_s_m=0": float(f"{max(rel_errs(Yr, ref_w)):.3e}")}
+                del pw_plan, Xw, Yw
+            ent["workload"] = f"n={Aw.n} nnz={Aw.nnz} p={pw}"
+            recursion[name] = ent
         log(f"recursion: {recursion}")
 
     # ---- other powers ----------------------------------------------------------------

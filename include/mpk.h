@@ -244,10 +244,12 @@ mpk_status mpk_plan_tile_deps(const mpk_plan *plan, int32_t *ranges, int32_t lin
  *                        the original levels that satisfies Eq. (5), s >= 1 =
  *                        a group of the levels of a subgraph refined s times
  *   dep_ptr[n_tiles+1]   first range of every tile's dependency list
- *   dep_rng[2*n_dep_ranges] inclusive tile ranges (lo, hi): before power q a
- *                        tile waits for power q-1 of these tiles, which hold
- *                        every row it reads and every row that shares a
- *                        128-byte line of a vector slice with them.
+ *   dep_rng[2*n_dep_ranges] inclusive tile ranges (lo, hi), ascending: before
+ *                        power q a tile waits for power q-1 of these tiles,
+ *                        which hold every row it reads and every row that
+ *                        shares a 128-byte line of a vector slice with them;
+ *                        ranges at most 31 tiles apart are merged, so a list
+ *                        may also name tiles between needed ones.
  * Level groups and the schedule of mpk_plan_arrays describe the unrefined
  * (stage-0) levels.  Errors: MPK_ERR_STATE for an unrefined plan. */
 mpk_status mpk_plan_units(const mpk_plan *plan, int32_t *unit_ptr, int32_t *unit_stage, int32_t *dep_ptr,

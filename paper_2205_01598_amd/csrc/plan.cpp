@@ -449,11 +449,16 @@ struct Refiner {
 };
 
 constexpr int64_t kKeyUnit = 1 << 24;  // wavefront key of one stage-0 level group
+// Dependency ranges of a refined tile with at most this many tiles between
+// them are merged (the tiles between are waited for too): a wait polls its
+// ranges one after another, each costing a memory round trip, while a
+// longer range costs only more flags in the same 64-flag loads.
+constexpr int32_t kDepMergeGap = 31;
 
 // Schedule of a refined plan: tiles inside the final groups ("units"),
 // per-tile dependency lists (every tile holding a column the tile reads, and
 // the tile itself, widened to whole 128-byte lines of an aligned N x k FP64
-// slice), and tickets ordered by a longest-path wavefront number of the
+// slice; ranges less than kDepMergeGap + 2 tiles apart merged), and tickets ordered by a longest-path wavefront number of the
 // (unit, power) nodes
 //   wf(u, 1) = key(u),  wf(u, q) = max(key(u) + skew*K*(q-1), max_v wf(v, q-1) + 1)
 // over the units v holding a dependency of a tile of u, K = kKeyUnit, then
@@ -519,7 +524,7 @@ mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &
                 const int64_t f = hp.tile_row[ts[a]], l = hp.tile_row[ts[b] + 1] - 1;
                 const int64_t f2 = f - f % Rl, l2 = std::min<int64_t>(n - 1, l + (Rl - 1 - l % Rl));
                 const int32_t lo = row_tile[f2], hi = row_tile[l2];
-                if (!out.empty() && lo <= out.back() + 1)
+                if (!out.empty() && lo <= out.back() + 1 + kDepMergeGap)
                     out.back() = std::max(out.back(), hi);
                 else {
                     out.push_back(lo);
@@ -982,13 +987,17 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            std::vector<uint8_t>(n, 0), {}, {}, {}, {}};
                 rf.order.reserve(n);
                 rf.refine(hp.perm, lp64, 0, 0, G0 * kKeyUnit);
-                perm0.swap(hp.perm);
-                hp.perm.swap(rf.order);
-                hp.unit_ptr.assign(rf.unit_rows.size() + 1, 0);
-                for (size_t u = 0; u < rf.unit_rows.size(); ++u) hp.unit_ptr[u + 1] = hp.unit_ptr[u] + rf.unit_rows[u];
-                hp.unit_stage = rf.unit_stage;
-                hp.unit_key = rf.unit_key;
-                hp.recursive = true;
+                // with no group refined the plan is the unrefined one
+                if (std::any_of(rf.unit_stage.begin(), rf.unit_stage.end(), [](int32_t s) { return s > 0; })) {
+                    perm0.swap(hp.perm);
+                    hp.perm.swap(rf.order);
+                    hp.unit_ptr.assign(rf.unit_rows.size() + 1, 0);
+                    for (size_t u = 0; u < rf.unit_rows.size(); ++u)
+                        hp.unit_ptr[u + 1] = hp.unit_ptr[u] + rf.unit_rows[u];
+                    hp.unit_stage = rf.unit_stage;
+                    hp.unit_key = rf.unit_key;
+                    hp.recursive = true;
+                }
             }
             hp.phase_seconds[0] = secs(ta, tb);
             hp.phase_seconds[1] = secs(tb, now());

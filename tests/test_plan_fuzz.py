@@ -22,7 +22,13 @@ def test_fuzz_plan(seed):
         _check_plan(A, p, C, root_mode, **opts)
     else:
         pl = Plan(A, p, C, upload=False, recursion_stages=stages, **opts)
-        _check_refined(pl, A, p, k=opts["nrhs"])
         operm, olp = O.bfs_levels(A, opts["root_mode"])
         fp, up, us = O.refine_levels(A, operm, olp, p, C, stages=stages)
         assert np.array_equal(pl.arrays()[0], fp)
+        if pl.info()["recursive"]:
+            _check_refined(pl, A, p, k=opts["nrhs"])
+        else:
+            # nothing refined: the plan is the unrefined one
+            assert np.all(us == 0)
+            root_mode = opts.pop("root_mode")
+            _check_plan(A, p, C, root_mode, **opts)

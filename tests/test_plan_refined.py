@@ -59,7 +59,7 @@ def _check_refined(pl, A, p, k=1, skew=1):
     for t in range(T):
         rng = dr[dp[t]:dp[t + 1]]
         assert np.all(rng[:, 0] <= rng[:, 1])
-        assert np.all(rng[1:, 0] > rng[:-1, 1] + 1)
+        assert np.all(rng[1:, 0] > rng[:-1, 1] + 1 + 31)       # closer ranges are merged
         covered = np.zeros(T, bool)
         for a, b in rng:
             covered[a:b + 1] = True
@@ -114,16 +114,23 @@ def test_refined_plan_default_tiles_and_skew(skew):
     _check_refined(pl, A, p, skew=skew)
 
 
-def test_refined_plan_without_violations_keeps_groups():
-    # a budget every level group satisfies: nothing is refined, the units are
-    # the level groups and the numbering is the breadth-first one
+def test_refined_plan_without_violations_is_unrefined():
+    # a budget every level group satisfies: nothing is refined (the oracle's
+    # units are the level groups), and the plan is the unrefined one
     A = W.stencil_2d(30, 5)
     pl = Plan(A, 3, 1 << 30, upload=False, recursion_stages=2)
-    perm, lp, gp, _ = pl.arrays()
-    up, us, _, _ = pl.units()
+    p0 = Plan(A, 3, 1 << 30, upload=False)
+    assert pl.info()["recursive"] == 0
+    with pytest.raises(MpkError):
+        pl.units()
     operm, olp = O.bfs_levels(A, 0)
-    assert np.array_equal(perm, operm)
-    assert np.array_equal(up, olp[gp]) and np.all(us == 0)
+    fp, up, us = O.refine_levels(A, operm, olp, 3, 1 << 30, stages=2)
+    assert np.all(us == 0)
+    for a, b in zip(pl.arrays(), p0.arrays()):
+        assert np.array_equal(a, b)
+    for a, b in zip(pl.tiles(), p0.tiles()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(pl.arrays()[0], fp)
 
 
 def test_refined_plan_rejections():
