@@ -43,6 +43,7 @@ extern "C" {
 
 #define MPK_MAX_POWER 32
 #define MPK_MAX_NRHS 32
+#define MPK_MAX_SKEW 32
 #define MPK_NUM_FEATURES 24
 
 typedef int32_t mpk_status;
@@ -85,9 +86,10 @@ typedef struct mpk_options {
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
                                  ((p+1)(b_nz nnz + 8 k rows) < fC); 0 = the paper's form */
     int32_t skew;             /* device ticket order over the (group, power) nodes: sorted by
-                                 g + skew*q, then q.  1 (default) = the Lp diagonals of Fig. 6;
-                                 2 puts every dependency a whole diagonal earlier (more work in
-                                 flight without waiting, about twice the reuse window) */
+                                 g + skew*q, then q; 1..MPK_MAX_SKEW.  1 (default) = the Lp
+                                 diagonals of Fig. 6; s >= 2 puts every dependency s - 1
+                                 diagonals earlier (more work in flight without waiting, a
+                                 reuse window of s*p + 1 groups instead of p + 1) */
     int32_t xcd_streams;      /* 1 (default): one ticket sequence for the whole grid.  8: the tiles
                                  of every level group are cut into 8 slices and slice s is run by
                                  workgroups with blockIdx % 8 == s (the XCD they are dispatched to

@@ -605,7 +605,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
     if (opt.reserved0 != 0 || opt.reserved[0] != 0 || opt.reserved[1] != 0)
         return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
-    if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+    if (opt.skew < 1 || opt.skew > MPK_MAX_SKEW) return fail(MPK_ERR_ARG, "skew must be in [1, 32]");
     if (opt.xcd_streams != 1 && opt.xcd_streams != 8) return fail(MPK_ERR_ARG, "xcd_streams must be 1 or 8");
     const int64_t n = hp.n;
     const int64_t L = (int64_t)hp.level_ptr.size() - 1;
@@ -934,7 +934,7 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.reserved0 != 0 || opt.reserved[0] != 0 || opt.reserved[1] != 0)
         return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
-    if (opt.skew < 1 || opt.skew > 8) return fail(MPK_ERR_ARG, "skew must be in [1, 8]");
+    if (opt.skew < 1 || opt.skew > MPK_MAX_SKEW) return fail(MPK_ERR_ARG, "skew must be in [1, 32]");
     if (opt.plan_on_device != 0 && opt.plan_on_device != 1) return fail(MPK_ERR_ARG, "plan_on_device must be 0 or 1");
     if (opt.force_acquire != 0 && opt.force_acquire != 1) return fail(MPK_ERR_ARG, "force_acquire must be 0 or 1");
     if (opt.recursion_stages < 0 || opt.recursion_stages > 16) return fail(MPK_ERR_ARG, "recursion_stages must be in [0, 16]");

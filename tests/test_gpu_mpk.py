@@ -92,6 +92,21 @@ def test_27pt_random(root_mode, p, tile, streams, skew):
     check_powers(Y, ref)
 
 
+@pytest.mark.parametrize("skew,streams,wg", [(8, 1, 0), (12, 1, 64), (32, 8, 0), (32, 1, 16)])
+def test_large_skews_thin_levels(skew, streams, wg):
+    # thin levels (2D 9-point stencil from a corner: 299 levels) and small
+    # level groups, with ticket skews that keep dependencies many diagonals
+    # back; the same sums as the baseline, so equal bit for bit
+    A = W.stencil_2d(150, 9)
+    x = W.uniform_vector(A.n, seed=skew)
+    ref = O.spmv_powers(A, x, 8)
+    Y, pl = run_mpk(A, x, 8, 1 << 17, root_mode=1, tile_nnz=400, skew=skew, xcd_streams=streams, workgroups=wg)
+    assert pl.info()["n_groups"] > 50
+    check_powers(Y, ref)
+    Yb, _ = run_mpk(A, x, 8, 1 << 17, baseline=True, root_mode=1, tile_nnz=400)
+    assert np.array_equal(Y, Yb)
+
+
 def test_integer_bit_exact():
     A = W.integer_stencil_27pt(20, seed=5)
     rng = np.random.default_rng(5)

@@ -129,7 +129,7 @@ def test_plan_27pt_random(n, root_mode, p, C):
     _check_plan(A, p, C, root_mode, tile_nnz=1500)
 
 
-@pytest.mark.parametrize("skew", [1, 2, 3])
+@pytest.mark.parametrize("skew", [1, 2, 3, 8, 32])
 def test_plan_skew_orders(skew):
     # skew 1 reproduces the Lp diagonal order of the schedule; any skew keeps
     # every dependency an earlier ticket
@@ -254,6 +254,9 @@ def test_plan_rejects_bad_input():
         Plan(A, 2, 1000, upload=False, reserved0=1)
     with pytest.raises(MpkError, match="MPK_ERR_ARG"):
         Plan(A, 2, 1000, upload=False, plan_on_device=2)
+    for skew in (0, 33):
+        with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+            Plan(A, 2, 1000, upload=False, skew=skew)
     with pytest.raises(MpkError, match="MPK_ERR_UNSUPPORTED"):
         Plan(A, 2, 1000, upload=False, nrhs=4, val_dtype="bf16")
 
