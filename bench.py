@@ -149,6 +149,7 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
     """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8.
     Low-precision errors are measured against the FP64 run of the same
     steps (whose agreement with the oracle the tests establish)."""
+    from paper_2205_01598_amd import tune
     from paper_2205_01598_amd.cheb import ChebPropagator
 
     A = W.anderson_3d(128, seed=0)
@@ -163,21 +164,16 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
         X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
         acc = torch.empty_like(X)
         tb = timed(torch, lambda: prop.step(X, acc, baseline=True), 20, 3)
-        # a small sweep of (C MB, tile nonzeros, skew); the matrix fits the
+        # the autotuner over a few (C, tile, skew); the matrix fits the
         # Infinity Cache, so smaller budgets than the headline's are tried
-        best = None
-        for C, tile, skew in ((256, 8192, 2), (128, 4096, 2), (64, 2048, 2), (32, 4096, 12), (64, 8192, 12)):
-            pl.retune(p, C << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=skew, tile_nnz=tile)
-            t = timed(torch, lambda: prop.step(X, acc), 10, 2)
-            if best is None or t < best[0]:
-                best = (t, (C, tile, skew))
-        C, tile, skew = best[1]
-        pl.retune(p, C << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=skew, tile_nnz=tile)
+        cands = [dict(cache_mb=C, tile_nnz=t, skew=s) for C, t, s in
+                 ((256, 8192, 2), (128, 4096, 2), (64, 2048, 2), (32, 4096, 12), (64, 8192, 12))]
+        cfg = tune.autotune(torch, pl, p, cands, lambda: prop.step(X, acc), reps=10, nrhs=2, val_dtype=dt)[0]
         tm = timed(torch, lambda: prop.step(X, acc), 20, 3)
         pl.status()
         ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
                "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1),
-               "config": {"cache_mb": C, "tile_nnz": tile, "skew": skew}}
+               "config": cfg}
         if dt == "f64":
             # the working set fits the 256 MB Infinity Cache: also time each
             # step after reading 512 MB of other data
@@ -239,7 +235,10 @@ def bench_heat(torch, Plan, W, dev):
 
 
 def bench_multi_rhs(torch, Plan, W, dev):
-    """Random geometric graph, N = 2M, ~16 nnz/row, p = 6, k = 4..32."""
+    """Random geometric graph, N = 2M, ~16 nnz/row, p = 6, k = 4..32, tile
+    and group shapes picked by the autotuner."""
+    from paper_2205_01598_amd import tune
+
     A, _ = W.random_geometric(2_000_000, 16.0, seed=0)
     out = {"workload": f"random geometric graph N=2M nnz={A.nnz}, row-normalised, p=6"}
     pl = Plan(A, 6, 256 << 20, root_mode=1)
@@ -250,15 +249,11 @@ def bench_multi_rhs(torch, Plan, W, dev):
         Y = torch.empty((6, A.n, k), dtype=torch.float64, device=dev)
         pl.retune(6, 256 << 20, root_mode=1, nrhs=k)
         tb = timed(torch, lambda: pl.run_baseline(X, Y), 5, 2)
-        best = None
-        for C, skew, tile in ((256, 2, 8192), (128, 2, 2048), (128, 3, 4096), (64, 3, 2048)):
-            pl.retune(6, C << 20, root_mode=1, nrhs=k, skew=skew, tile_nnz=tile)
-            t = timed(torch, lambda: pl.run(X, Y), 5, 2)
-            if best is None or t < best[0]:
-                best = (t, {"cache_mb": C, "skew": skew, "tile_nnz": tile})
-        pl.status()
-        out[f"k{k}"] = {"mpk_ms": round(best[0], 4), "baseline_ms": round(tb, 4), "speedup": round(tb / best[0], 3),
-                        "gflops": round(2.0 * A.nnz * 6 * k / best[0] / 1e6, 1), "config": best[1]}
+        cands = [dict(cache_mb=C, skew=s, tile_nnz=t) for C, s, t in
+                 ((256, 2, 8192), (128, 2, 2048), (128, 3, 4096), (64, 3, 2048))]
+        cfg, tm, _ = tune.autotune(torch, pl, 6, cands, lambda: pl.run(X, Y), nrhs=k)
+        out[f"k{k}"] = {"mpk_ms": round(tm, 4), "baseline_ms": round(tb, 4), "speedup": round(tb / tm, 3),
+                        "gflops": round(2.0 * A.nnz * 6 * k / tm / 1e6, 1), "config": cfg}
         del X, Y
     return out
 
@@ -267,6 +262,8 @@ def bench_thin_levels(torch, Plan, W, dev):
     """2D 9-point stencil on a 4096^2 grid (N = 16.8M, 151M nonzeros, 1.8 GB
     of FP64 CSR): 4096 levels of at most 4096 rows, so the level groups can
     be small and a large ticket skew keeps enough work in flight.  p = 8."""
+    from paper_2205_01598_amd import tune
+
     A = W.stencil_2d(4096, 9)
     p = 8
     x = W.uniform_vector(A.n, seed=0)
@@ -276,21 +273,17 @@ def bench_thin_levels(torch, Plan, W, dev):
     Y = torch.empty((p, A.n), dtype=torch.float64, device=dev)
     tb = timed(torch, lambda: pl.run_baseline(X, Y), 10, 2)
     ref = Y.clone()
-    runs = {}
-    best = None
-    for C, skew, tile in ((256, 2, 8192), (32, 12, 8192), (16, 24, 8192), (32, 8, 4096)):
-        pl.retune(p, C << 20, root_mode=1, skew=skew, tile_nnz=tile, workgroups=1024)
-        t = timed(torch, lambda: pl.run(X, Y), 10, 2)
-        pl.status()
-        same = bool(torch.equal(Y, ref))
-        runs[f"C{C}_s{skew}_t{tile}"] = {"ms": round(t, 4), "level_groups": pl.info()["n_groups"],
-                                         "bit_equal_to_baseline": same}
-        if best is None or t < best[0]:
-            best = (t, {"cache_mb": C, "skew": skew, "tile_nnz": tile, "workgroups": 1024})
+    cands = [dict(cache_mb=C, skew=s, tile_nnz=t, workgroups=1024) for C, s, t in
+             ((256, 2, 8192), (32, 12, 8192), (16, 24, 8192), (32, 8, 4096))]
+    cfg, tm, timings = tune.autotune(torch, pl, p, cands, lambda: pl.run(X, Y), reps=10)
+    runs = {f"C{c['cache_mb']}_s{c['skew']}_t{c['tile_nnz']}": round(t, 4) for c, t in timings}
+    pl.run(X, Y)
+    pl.status()
     flop = 2.0 * A.nnz * p
     return {"workload": f"2D 9-point stencil 4096^2, n={A.n} nnz={A.nnz}, p={p}", "levels": pl.info()["n_levels"],
-            "mpk_ms": round(best[0], 4), "baseline_ms": round(tb, 4), "speedup": round(tb / best[0], 3),
-            "gflops": round(flop / best[0] / 1e6, 1), "config": best[1], "runs": runs}
+            "level_groups": pl.info()["n_groups"], "mpk_ms": round(tm, 4), "baseline_ms": round(tb, 4),
+            "speedup": round(tb / tm, 3), "gflops": round(flop / tm / 1e6, 1), "config": cfg,
+            "bit_equal_to_baseline": bool(torch.equal(Y, ref)), "runs_ms": runs}
 
 
 def probe():
@@ -386,7 +379,7 @@ def main():
     import torch
 
     import workloads as W
-    from paper_2205_01598_amd import Plan, Spmv
+    from paper_2205_01598_amd import Plan, Spmv, tune
 
     dev = torch.device("cuda:0")
     p = args.p
@@ -425,20 +418,13 @@ def main():
     log(f"baselines (ms): {base}")
 
     # ---- MPK configuration: small sweep on the same levels ------------------------
-    cands = [dict(skew=2, cache=256, tile=8192), dict(skew=2, cache=256, tile=6144),
-             dict(skew=2, cache=256, tile=4096), dict(skew=2, cache=512, tile=8192)]
+    cands = [dict(cache_mb=256, skew=2, tile_nnz=8192), dict(cache_mb=256, skew=2, tile_nnz=6144),
+             dict(cache_mb=256, skew=2, tile_nnz=4096), dict(cache_mb=512, skew=2, tile_nnz=8192)]
     if args.quick:
         cands = cands[:1]
-    best = None
-    for c in cands:
-        plan.retune(p, c["cache"] << 20, root_mode=1, skew=c["skew"], tile_nnz=c["tile"])
-        ms = timed(torch, lambda: plan.run(X, Y), 5, 2)
-        plan.status()
+    cfg, _, timings = tune.autotune(torch, plan, p, cands, lambda: plan.run(X, Y))
+    for c, ms in timings:
         log(f"mpk {c}: {ms:.3f} ms")
-        if best is None or ms < best[0]:
-            best = (ms, c)
-    cfg = best[1]
-    plan.retune(p, cfg["cache"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile"])
     info = plan.info()
 
     # ---- calibration copy for the HBM counters: 256 MiB read + 256 MiB written ---------
@@ -477,7 +463,7 @@ def main():
     if not args.only_main:
         for sm in (1, 2):
             t0 = time.time()
-            pr = Plan(A, p, cfg["cache"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile"],
+            pr = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile_nnz"],
                       recursion_stages=sm)
             ps = time.time() - t0
             rperm = pr.arrays()[0].astype(np.int64)
@@ -530,15 +516,9 @@ def main():
         Yq = torch.empty((q, n), dtype=torch.float64, device=dev)
         plan.retune(q, 256 << 20, root_mode=1)
         tb = timed(torch, lambda: plan.run_baseline(X, Yq), 5, 2)
-        bestq = None
-        for c in cands:
-            plan.retune(q, c["cache"] << 20, root_mode=1, skew=c["skew"], tile_nnz=c["tile"])
-            t = timed(torch, lambda: plan.run(X, Yq), 5, 2)
-            if bestq is None or t < bestq[0]:
-                bestq = (t, c)
-        plan.status()
-        other[f"p{q}"] = {"ms": round(bestq[0], 4), "gflops": round(2.0 * nnz * q / bestq[0] / 1e6, 1),
-                          "baseline_ms": round(tb, 4), "speedup": round(tb / bestq[0], 3), "config": bestq[1]}
+        cq, tq, _ = tune.autotune(torch, plan, q, cands, lambda: plan.run(X, Yq))
+        other[f"p{q}"] = {"ms": round(tq, 4), "gflops": round(2.0 * nnz * q / tq / 1e6, 1),
+                          "baseline_ms": round(tb, 4), "speedup": round(tb / tq, 3), "config": cq}
         del Yq
 
     # ---- CPU oracle (FP64, single thread) ------------------------------------------
@@ -553,24 +533,19 @@ def main():
     mixed = {}
     if not args.no_mixed:
         for dt in ("f32", "bf16"):
-            pm = Plan(A, p, cfg["cache"] << 20, root_mode=1, val_dtype=dt, skew=cfg["skew"],
-                      tile_nnz=cfg["tile"])
+            pm = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, val_dtype=dt, skew=cfg["skew"],
+                      tile_nnz=cfg["tile_nnz"])
             tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
             # the same small sweep as for FP64 (smaller values shift the best tile)
-            mbest = None
-            for c in cands + ([] if args.quick else [dict(skew=2, cache=256, tile=12288),
-                                                     dict(skew=2, cache=256, tile=16384)]):
-                pm.retune(p, c["cache"] << 20, root_mode=1, val_dtype=dt, skew=c["skew"], tile_nnz=c["tile"])
-                t = timed(torch, lambda: pm.run(X, Y), 5, 2)
-                if mbest is None or t < mbest[0]:
-                    mbest = (t, c)
-            pm.retune(p, mbest[1]["cache"] << 20, root_mode=1, val_dtype=dt, skew=mbest[1]["skew"],
-                      tile_nnz=mbest[1]["tile"])
+            mc = tune.autotune(torch, pm, p, cands + ([] if args.quick else
+                                                      [dict(cache_mb=256, skew=2, tile_nnz=12288),
+                                                       dict(cache_mb=256, skew=2, tile_nnz=16384)]),
+                               lambda: pm.run(X, Y), val_dtype=dt)[0]
             tm = timed(torch, lambda: pm.run(X, Y), 10, 3)
             pm.status()
             ent = {"ms": round(tm, 4), "gflops": round(flop / tm / 1e6, 1), "baseline_ms": round(tbm, 4),
                    "speedup": round(tbm / tm, 3), "speedup_vs_fp64_baseline": round(t_base / tm, 3),
-                   "config": mbest[1]}
+                   "config": mc}
             Ym = np.empty((p, n))
             Ym[:, perm] = Y.cpu().numpy()
             ent["rel_err_vs_fp64_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, Yh)]
@@ -607,7 +582,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"27-point stencil {args.n}^3, random relabelling, FP64, single vector",
                    "n": n, "nnz": nnz, "p": p, "root": "pseudo-peripheral",
-                   "cache_budget_mb": cfg["cache"], "skew": cfg["skew"], "tile_nnz": cfg["tile"],
+                   "cache_budget_mb": cfg["cache_mb"], "skew": cfg["skew"], "tile_nnz": cfg["tile_nnz"],
                    "workgroups": info["workgroups"], "levels": info["n_levels"],
                    "level_groups": info["n_groups"], "seed": args.seed},
         "speedup_vs_spmv": round(t_base / ms, 3),

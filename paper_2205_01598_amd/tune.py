@@ -61,6 +61,42 @@ def _apply(plan: Plan, p: int, c: dict, nrhs: int = 1):
                 workgroups=int(c["workgroups"]), nrhs=nrhs)
 
 
+def autotune(torch, plan: Plan, p: int, candidates, run, reps: int = 5, warmup: int = 2, **fixed):
+    """The exhaustive autotuner: retunes ``plan`` (same levels, no new BFS) to
+    every candidate configuration, times ``run()`` (one level-blocked run on
+    the caller's device buffers) and leaves the plan at the fastest.
+    A candidate is a dict of ``cache_mb`` and any of ``skew``, ``tile_nnz``,
+    ``workgroups`` (missing keys take the library's defaults); ``fixed``
+    holds further retune options shared by all (``nrhs``, ``val_dtype``,
+    ``root_mode``, default 1).  Returns (best configuration, its mean time in
+    ms, [(configuration, ms)] for every candidate)."""
+    fixed.setdefault("root_mode", 1)
+
+    def apply(c):
+        opts = dict(fixed)
+        opts.update({k: int(v) for k, v in c.items() if k != "cache_mb"})
+        plan.retune(p, int(c["cache_mb"]) << 20, **opts)
+
+    timings = []
+    for c in candidates:
+        apply(c)
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            run()
+        e.record()
+        torch.cuda.synchronize()
+        plan.status()
+        timings.append((dict(c), s.elapsed_time(e) / reps))
+    best = min(timings, key=lambda r: r[1])
+    apply(best[0])
+    return best[0], best[1], timings
+
+
 def time_run(torch, plan: Plan, X, Y, reps: int = 5, warmup: int = 2) -> float:
     for _ in range(warmup):
         plan.run(X, Y)

@@ -71,3 +71,39 @@ def test_best_static_is_grid_member_and_optimal_on_its_records():
             ms = 1.0 if i == 0 else (0.5 if i == 3 else float(rng.uniform(0.6, 1.5)))
             recs.append({"seed": seed, "spec": {}, "p": 4, "features": [0.0] * 24, "config": c, "ms": ms})
     assert tune.best_static(recs) == grid[3]
+
+
+@pytest.mark.gpu
+def test_autotune_picks_fastest_and_leaves_plan_there():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle as O
+    import workloads as W
+    from paper_2205_01598_amd import Plan
+
+    A = W.stencil_2d(160, 9)
+    p = 6
+    x = W.uniform_vector(A.n, seed=3)
+    pl = Plan(A, p, 1 << 20, root_mode=1)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).cuda()
+    Y = torch.empty((p, A.n), dtype=torch.float64, device="cuda")
+    cands = [dict(cache_mb=1, skew=1, tile_nnz=300), dict(cache_mb=4, skew=2, tile_nnz=2000),
+             dict(cache_mb=1, skew=12, tile_nnz=1000, workgroups=64)]
+    cfg, ms, timings = tune.autotune(torch, pl, p, cands, lambda: pl.run(X, Y), reps=3, warmup=1)
+    assert [c for c, _ in timings] == cands
+    assert (cfg, ms) == min(timings, key=lambda r: r[1])
+    # the plan is left at the chosen configuration: same tiles and tickets
+    # as a fresh plan made with it
+    fresh = Plan(A, p, cfg["cache_mb"] << 20, upload=False, root_mode=1,
+                 **{k: v for k, v in cfg.items() if k != "cache_mb"})
+    for a, b in zip(pl.tiles(), fresh.tiles()):
+        assert np.array_equal(a, b)
+    pl.run(X, Y)
+    pl.status()
+    out = np.empty((p, A.n))
+    out[:, perm] = Y.cpu().numpy()
+    ref = O.spmv_powers(A, x, p)
+    for q in range(p):
+        assert np.linalg.norm(out[q] - ref[q]) <= 1e-12 * np.linalg.norm(ref[q])
