@@ -3,8 +3,9 @@
 //  * spmv_kernel      one SpMV over all rows (the baseline of Sec. 3.1,
 //                     Fig. 2); p launches back to back give the baseline MPK.
 //  * mpk_persistent   the level-blocked MPK (Sec. 4.2-4.3): a persistent grid
-//                     draws tickets from one counter in the Lp diagonal order
-//                     of the level groups (Fig. 6); a ticket is one device
+//                     draws tickets, through striped counters, in the order of
+//                     the (level group, power) nodes by g + skew*q (skew 1 =
+//                     the Lp diagonals of Fig. 6); a ticket is one device
 //                     tile (a row range inside a level group) at one power.
 //                     Before computing power q of a tile, one wavefront polls
 //                     the "power q-1 done" flags of every tile that holds a
