@@ -317,7 +317,7 @@ def bench_learned_tuner(torch, plan, X, Y, p, log):
     train, test = tune.split_seeds(recs)
     t0 = time.time()
     tuner = tune.LearnedTuner(hidden=64, seed=0)
-    loss = tuner.fit(train, steps=3000)
+    loss = tuner.fit(train, steps=6000)
     out = {"train_matrices": len({r["seed"] for r in train}), "held_out_matrices": len({r["seed"] for r in test}),
            "train_seconds": round(time.time() - t0, 2), "final_train_loss": round(loss, 5),
            "held_out": tune.evaluate(tuner, test, tune.best_static(train))}

@@ -30,7 +30,7 @@ from .mpk import Plan
 
 # configuration space: level-group budget C, ticket skew, tile size, grid
 CACHE_MB = (32, 128, 512)
-SKEWS = (1, 2)
+SKEWS = (1, 2, 4, 8)
 TILES = (2048, 8192)
 GRIDS = (1024, 2048)
 DEFAULT = {"cache_mb": 256, "skew": 1, "tile_nnz": 0, "workgroups": 0}
@@ -46,7 +46,7 @@ def config_grid():
 def encode_config(c) -> np.ndarray:
     tile = c["tile_nnz"] or 8192  # the library's default tile
     wg = c["workgroups"] or 2048  # all resident workgroups of the chunk kernel
-    return np.array([math.log2(c["cache_mb"] / 32.0) / 4.0, float(c["skew"] - 1),
+    return np.array([math.log2(c["cache_mb"] / 32.0) / 4.0, math.log2(c["skew"]) / 3.0,
                      math.log2(tile / 2048.0) / 4.0, math.log2(wg / 1024.0)], dtype=np.float64)
 
 
@@ -170,6 +170,8 @@ def load_db(path: str):
         for line in fh:
             r = json.loads(line)
             if "times_ms" in r:
+                if len(r["times_ms"]) != len(grid):
+                    raise ValueError(f"{path}: {len(r['times_ms'])} timings per case, the grid has {len(grid)}")
                 for c, ms in zip(grid, r["times_ms"]):
                     out.append({"seed": r["seed"], "spec": r["spec"], "p": r["p"], "features": r["features"],
                                 "config": c, "ms": ms})
@@ -321,7 +323,7 @@ class LearnedTuner:
         f = (np.asarray(feats, np.float64) - self.mu) / self.sd
         return np.stack([np.concatenate([f, encode_config(c)]) for c in configs])
 
-    def fit(self, records, steps=3000, lr=3e-3):
+    def fit(self, records, steps=6000, lr=3e-3):
         groups = _group(records)
         F = np.array([g[0]["features"] for g in groups.values()], np.float64)
         self.mu = F.mean(0)

@@ -46,13 +46,13 @@ def test_learned_tuner_beats_default_on_held_out():
     recs = tune.load_db(DB)
     train, test = tune.split_seeds(recs)
     tuner = tune.LearnedTuner(hidden=64, seed=0)
-    loss = tuner.fit(train, steps=3000)
+    loss = tuner.fit(train, steps=6000)
     assert math.isfinite(loss)
     static = tune.best_static(train)
     m = tune.evaluate(tuner, test, static)
     # the untuned default (C = 256 MB, skew 1, grid = all resident
     # workgroups) is measurably worse than the choice of the trained network
-    # (on this database the sweep's best is 1.17x the default, geomean)
+    # (on this database the sweep's best is 1.20x the default, geomean)
     assert m["geomean_gain_over_default"] > 1.05, m
     # the features matter: the per-matrix choice beats the one configuration
     # that is best on the training matrices as a whole
