@@ -5,7 +5,7 @@ import numpy as np
 
 import workloads as W
 
-N_CASES = 24
+N_CASES = 32
 
 
 def case(seed):
@@ -34,4 +34,7 @@ def case(seed):
     if rng.integers(0, 3) == 0:
         opts["workgroups"] = int(rng.integers(1, 600))
     x = rng.uniform(-1, 1, (A.n, k)) if k > 1 else rng.uniform(-1, 1, A.n)
+    if seed >= 24:
+        # large ticket skews (drawn last, so the cases below 24 are unchanged)
+        opts["skew"] = int(rng.choice([4, 8, 16, 32]))
     return A, p, C, opts, x
