@@ -339,9 +339,23 @@ class LearnedTuner:
         return self.net.train(X, y, steps=steps, lr=lr)
 
     def choose(self, features, configs=None):
+        return self.shortlist(features, 1, configs)[0]
+
+    def shortlist(self, features, m, configs=None):
+        """The m configurations with the smallest predicted time, best first."""
         configs = configs or config_grid()
         pred = self.net.predict(self._inputs(features, configs))
-        return configs[int(np.argmin(pred))]
+        return [configs[int(i)] for i in np.argsort(pred, kind="stable")[:m]]
+
+    def tune(self, torch, plan: Plan, p: int, run, m: int = 3, **fixed):
+        """Learned choice checked by measurement: the plan's features (taken
+        at the default configuration, as in the sweep), the model's m best
+        configurations, then ``autotune`` over those m on the caller's run.
+        m = 1 is the model alone; m = len(config_grid()) is the exhaustive
+        sweep.  Returns what ``autotune`` returns."""
+        _apply(plan, p, DEFAULT, nrhs=int(fixed.get("nrhs", 1)))
+        feats = plan_features(plan)
+        return autotune(torch, plan, p, self.shortlist(feats, m), run, **fixed)
 
 
 def best_static(records):
@@ -358,14 +372,19 @@ def best_static(records):
     return json.loads(best)
 
 
-def evaluate(tuner: LearnedTuner, records, static=None):
+def evaluate(tuner: LearnedTuner, records, static=None, shortlist=(3,)):
     """Held-out quality: the measured time of the chosen configuration against
     the sweep's best, the untuned default and (if given) one static
-    configuration, per (matrix, p)."""
+    configuration, per (matrix, p); for every m in ``shortlist``, the same for
+    the fastest (by the recorded times) of the model's m best configurations,
+    which is what ``LearnedTuner.tune`` measures."""
     ratios, gains, within, sgains = [], [], 0, []
+    short = {m: [] for m in shortlist}
     groups = _group(records)
     for g in groups.values():
-        cfg = tuner.choose(g[0]["features"], [r["config"] for r in g])
+        cfgs = [r["config"] for r in g]
+        ranked = tuner.shortlist(g[0]["features"], max((1,) + tuple(shortlist)), cfgs)
+        cfg = ranked[0]
         t = {json.dumps(r["config"], sort_keys=True): r["ms"] for r in g}
         tpick = t[json.dumps(cfg, sort_keys=True)]
         tbest = min(t.values())
@@ -373,6 +392,8 @@ def evaluate(tuner: LearnedTuner, records, static=None):
         ratios.append(tpick / tbest)
         gains.append(tdef / tpick)
         within += tpick <= 1.05 * tbest
+        for m in shortlist:
+            short[m].append(min(t[json.dumps(c, sort_keys=True)] for c in ranked[:m]) / tbest)
         if static is not None:
             sgains.append(tdef / t[json.dumps(static, sort_keys=True)])
     n = len(groups)
@@ -383,6 +404,9 @@ def evaluate(tuner: LearnedTuner, records, static=None):
            "geomean_best_gain_over_default": float(np.exp(np.mean(np.log(
                [[r["ms"] for r in g if r["config"] == DEFAULT][0] / min(r["ms"] for r in g)
                 for g in groups.values()]))))}
+    for m, v in short.items():
+        out[f"shortlist{m}_geomean_over_best"] = float(np.exp(np.mean(np.log(v))))
+        out[f"shortlist{m}_within_5pct_of_best"] = float(np.mean(np.array(v) <= 1.05))
     if static is not None:
         out["static_config"] = static
         out["geomean_static_gain_over_default"] = float(np.exp(np.mean(np.log(sgains))))

@@ -59,6 +59,47 @@ def test_learned_tuner_beats_default_on_held_out():
     assert m["geomean_gain_over_default"] > 1.02 * m["geomean_static_gain_over_default"], m
     # and the choice is close to the exhaustive sweep's best
     assert m["geomean_pick_over_best"] < 1.08, m
+    # measuring the model's three best configurations comes closer still
+    assert m["shortlist3_geomean_over_best"] <= m["geomean_pick_over_best"], m
+    assert m["shortlist3_geomean_over_best"] < 1.05, m
+
+
+class _RankNet:
+    """Stand-in network: predicts a given score per configuration."""
+
+    def __init__(self, score):
+        self.score = score
+
+    def predict(self, X):
+        return np.array([self.score(tuple(row[-4:])) for row in X])
+
+
+def test_shortlist_and_evaluate_on_synthetic_records():
+    grid = tune.config_grid()
+    rng = np.random.default_rng(1)
+    recs = []
+    for seed in range(5):
+        ms = rng.uniform(0.5, 2.0, len(grid))
+        for c, t in zip(grid, ms):
+            recs.append({"seed": seed, "spec": {}, "p": 4, "features": [0.0] * 24, "config": c, "ms": float(t)})
+    enc = {tuple(tune.encode_config(c)): i for i, c in enumerate(grid)}
+    t = tune.LearnedTuner()
+    t.mu, t.sd = np.zeros(24), np.ones(24)
+    # a model that ranks by the true times of seed 0 is exact there
+    times0 = [r["ms"] for r in recs if r["seed"] == 0]
+    t.net = _RankNet(lambda e: times0[enc[e]])
+    order = sorted(range(len(grid)), key=lambda i: times0[i])
+    assert t.shortlist([0.0] * 24, 4) == [grid[i] for i in order[:4]]
+    assert t.choose([0.0] * 24) == grid[order[0]]
+    m = tune.evaluate(t, [r for r in recs if r["seed"] == 0], shortlist=(1, 3))
+    assert m["geomean_pick_over_best"] == 1.0 and m["shortlist3_geomean_over_best"] == 1.0
+    # the reversed ranking: the shortlist of m is the best of the m slowest
+    t.net = _RankNet(lambda e: -times0[enc[e]])
+    m = tune.evaluate(t, [r for r in recs if r["seed"] == 0], shortlist=(1, 3))
+    srt = sorted(times0)
+    assert np.isclose(m["geomean_pick_over_best"], srt[-1] / srt[0])
+    assert np.isclose(m["shortlist3_geomean_over_best"], srt[-3] / srt[0])
+    assert np.isclose(m["shortlist1_geomean_over_best"], m["geomean_pick_over_best"])
 
 
 def test_best_static_is_grid_member_and_optimal_on_its_records():
