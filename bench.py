@@ -537,15 +537,18 @@ def main():
     # ---- mixed precision ------------------------------------------------------------
     mixed = {}
     if not args.no_mixed:
-        for dt in ("f32", "bf16"):
-            pm = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, val_dtype=dt, skew=cfg["skew"],
+        # FP32 / BF16 storage with FP32 arithmetic (the default), and the same
+        # storage with FP64 arithmetic ("_acc64": x read in FP64, products and
+        # sums in FP64)
+        for dt, acc in (("f32", 0), ("bf16", 0), ("f32", 1), ("bf16", 1)):
+            pm = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, val_dtype=dt, accum_f64=acc, skew=cfg["skew"],
                       tile_nnz=cfg["tile_nnz"])
             tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
             # the same small sweep as for FP64 (smaller values shift the best tile)
             mc = tune.autotune(torch, pm, p, cands + ([] if args.quick else
                                                       [dict(cache_mb=256, skew=2, tile_nnz=12288),
                                                        dict(cache_mb=256, skew=2, tile_nnz=16384)]),
-                               lambda: pm.run(X, Y), val_dtype=dt)[0]
+                               lambda: pm.run(X, Y), val_dtype=dt, accum_f64=acc)[0]
             tm = timed(torch, lambda: pm.run(X, Y), 10, 3)
             pm.status()
             ent = {"ms": round(tm, 4), "gflops": round(flop / tm / 1e6, 1), "baseline_ms": round(tbm, 4),
@@ -554,7 +557,7 @@ def main():
             Ym = np.empty((p, n))
             Ym[:, perm] = Y.cpu().numpy()
             ent["rel_err_vs_fp64_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, Yh)]
-            mixed[dt] = ent
+            mixed[dt + ("_acc64" if acc else "")] = ent
             del pm
 
     extra = {}

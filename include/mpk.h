@@ -107,7 +107,12 @@ typedef struct mpk_options {
                                  0 (default): no refinement.  A refined plan orders its tickets by
                                  a longest-path wavefront number over per-tile dependency lists and
                                  cannot be retuned (the numbering depends on p and C). */
-    int32_t reserved[2];      /* must be 0 */
+    int32_t accum_f64;        /* FP32 / BF16 values only.  0 (default): the input vector is rounded
+                                 to FP32 and products and row sums are formed in FP32, each power
+                                 stored in FP64.  1: values widened to FP64, products and row sums
+                                 in FP64 (the input vector as given); only the matrix storage is
+                                 reduced.  FP64 values always use FP64 (the flag is ignored). */
+    int32_t reserved;         /* must be 0 */
 } mpk_options;
 
 /* Plan summary (mpk_plan_query). */

@@ -8,6 +8,8 @@
  *                        (the baseline MPK of Sec. 3.1, Fig. 2), which is the
  *                        plain definition of what any MPK computes:
  *                        y_p = A^p x for p = 1..p_m, every y_p kept.
+ *   orc_round_values     matrix values rounded to FP32 / BF16 storage, as FP64
+ *                        (with orc_spmv_powers: the FP64-arithmetic variant)
  *   orc_spmv_powers_lowp the same with matrix values and inputs rounded to a
  *                        lower precision and the products summed in FP32
  *                        (the mixed-precision variant), written as its
@@ -87,6 +89,21 @@ static float to_bf16(float f)
  * The GPU path uses fused multiply-adds and another summation order, so the
  * two agree to f32 rounding, not bit for bit.
  */
+/* Matrix values as a lower-precision storage holds them, widened back to
+ * FP64: vdtype 1 = FP32 (round to nearest even), 2 = BF16 (FP32 first, then
+ * the upper 16 bits with round to nearest even).  With these values the
+ * FP64-arithmetic variant of the mixed-precision product is the plain
+ * definition: p back-to-back FP64 SpMVs (orc_spmv_powers) on them. */
+int orc_round_values(int64_t nnz, const double *val, int32_t vdtype, double *out)
+{
+    if (nnz < 0 || vdtype < 1 || vdtype > 2) return -1;
+    for (int64_t j = 0; j < nnz; ++j) {
+        float f = to_f32(val[j]);
+        out[j] = (double)((vdtype == 2) ? to_bf16(f) : f);
+    }
+    return 0;
+}
+
 int orc_spmv_powers_lowp(int64_t n, const int64_t *rowptr, const int32_t *col,
                          const double *val, int32_t vdtype, int32_t k, int32_t p,
                          const double *x, double *y)

@@ -12,6 +12,8 @@ Functions and the passages they follow
                      back-to-back CRS SpMVs.  This is the exact target every
                      MPK variant must reproduce (level blocking only reorders
                      these operations, Sec. 4.2).
+  round_values       values as FP32 / BF16 storage holds them, as FP64; with
+                     spmv_powers the FP64-arithmetic mixed-precision variant
   spmv_powers_lowp   the same product with matrix values stored in FP32 or
                      BF16 and FP32 accumulation (an extension, not in the
                      paper; parity for it is tolerance-based, not exact).
@@ -57,6 +59,8 @@ def _load():
     lib.orc_spmv_powers_lowp.restype = ctypes.c_int
     lib.orc_spmv_powers_lowp.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]
+    lib.orc_round_values.restype = ctypes.c_int
+    lib.orc_round_values.argtypes = [ctypes.c_int64, _f64p, ctypes.c_int32, _f64p]
     lib.orc_bfs_distances.restype = ctypes.c_int
     lib.orc_bfs_distances.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i64p]
     lib.orc_peripheral_root.restype = ctypes.c_int64
@@ -113,6 +117,19 @@ def spmv_powers_lowp(A, x, p: int, vdtype: str) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_spmv_powers_lowp failed")
     return y.reshape((p, A.n) if x.ndim == 1 else (p, A.n, k))
+
+
+def round_values(A, vdtype: str):
+    """A with its values rounded as FP32 ('f32') or BF16 ('bf16') storage
+    holds them (round to nearest even; BF16 via FP32), widened back to FP64.
+    spmv_powers on the result is the FP64-arithmetic variant of the
+    mixed-precision product: reduced storage, FP64 products and sums."""
+    code = {"f32": 1, "bf16": 2}[vdtype]
+    rowptr, col, val = _arrs(A)
+    out = np.empty(A.nnz, dtype=np.float64)
+    if _load().orc_round_values(A.nnz, _p(val, _f64p), code, _p(out, _f64p)):
+        raise ValueError("orc_round_values failed")
+    return type(A)(A.n, A.rowptr, A.col, out)
 
 
 # ----------------------------------------------------------------------------

@@ -43,7 +43,8 @@ class mpk_options(ctypes.Structure):
                 ("watchdog_spins", ctypes.c_int64), ("budget_vectors", ctypes.c_int32),
                 ("skew", ctypes.c_int32), ("xcd_streams", ctypes.c_int32),
                 ("plan_on_device", ctypes.c_int32), ("force_acquire", ctypes.c_int32),
-                ("recursion_stages", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("recursion_stages", ctypes.c_int32), ("accum_f64", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class mpk_plan_info(ctypes.Structure):

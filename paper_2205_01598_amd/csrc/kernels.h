@@ -28,6 +28,14 @@ constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
 struct bf16_t {
     uint16_t bits;
 };
+// The same storage with FP64 arithmetic: values widened to FP64, the input
+// vector read as it is, products and row sums in FP64.
+struct f32w_t {
+    float v;
+};
+struct bf16w_t {
+    uint16_t bits;
+};
 
 template <typename VT>
 struct AccumType {
@@ -37,11 +45,23 @@ template <>
 struct AccumType<double> {
     using T = double;
 };
+template <>
+struct AccumType<f32w_t> {
+    using T = double;
+};
+template <>
+struct AccumType<bf16w_t> {
+    using T = double;
+};
 
 __device__ __forceinline__ double load_value(const double *v, int64_t j) { return v[j]; }
 __device__ __forceinline__ float load_value(const float *v, int64_t j) { return v[j]; }
 __device__ __forceinline__ float load_value(const bf16_t *v, int64_t j) {
     return __uint_as_float(((uint32_t)v[j].bits) << 16);
+}
+__device__ __forceinline__ double load_value(const f32w_t *v, int64_t j) { return (double)v[j].v; }
+__device__ __forceinline__ double load_value(const bf16w_t *v, int64_t j) {
+    return (double)__uint_as_float(((uint32_t)v[j].bits) << 16);
 }
 
 // Coefficients of the recurrence epilogue, passed by value in the kernel

@@ -61,7 +61,7 @@ struct mpk_plan {
 
 struct mpk_spmv {
     int64_t n = 0, nnz = 0;
-    int32_t dtype = MPK_F64, nrhs = 1;
+    int32_t dtype = MPK_F64, nrhs = 1, acc64 = 0;
     int64_t nchunks = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_chunk = nullptr;
     void *d_val = nullptr;
@@ -466,7 +466,8 @@ struct Dispatch {
 };
 
 // What is compiled: FP64 for every k in {1,2,4,8,16,32} (recurrence for k <= 2);
-// FP32 and BF16 values for k in {1, 2} with and without the recurrence.
+// FP32 and BF16 values, with FP32 or FP64 arithmetic, for k in {1, 2} with and
+// without the recurrence.
 template <typename VT, bool REC>
 struct ByK {
     template <typename F>
@@ -487,12 +488,17 @@ struct ByK {
     }
 };
 
+// acc64: FP32 / BF16 values with FP64 arithmetic (mpk_options.accum_f64)
 template <typename F>
-hipError_t dispatch_all(int dtype, int K, bool rec, F &&f) {
+hipError_t dispatch_all(int dtype, int acc64, int K, bool rec, F &&f) {
     switch (dtype) {
         case MPK_F64: return rec ? ByK<double, true>::call(K, f) : ByK<double, false>::call(K, f);
-        case MPK_F32: return rec ? ByK<float, true>::call(K, f) : ByK<float, false>::call(K, f);
-        case MPK_BF16: return rec ? ByK<bf16_t, true>::call(K, f) : ByK<bf16_t, false>::call(K, f);
+        case MPK_F32:
+            if (acc64) return rec ? ByK<f32w_t, true>::call(K, f) : ByK<f32w_t, false>::call(K, f);
+            return rec ? ByK<float, true>::call(K, f) : ByK<float, false>::call(K, f);
+        case MPK_BF16:
+            if (acc64) return rec ? ByK<bf16w_t, true>::call(K, f) : ByK<bf16w_t, false>::call(K, f);
+            return rec ? ByK<bf16_t, true>::call(K, f) : ByK<bf16_t, false>::call(K, f);
     }
     return hipErrorInvalidValue;
 }
@@ -782,7 +788,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     // grid: all co-resident workgroups unless the caller fixes it
     int occ = 0;
     const void *sym = nullptr;
-    (void)dispatch_all(h.opt.val_dtype, h.opt.nrhs, false, [&](auto d) {
+    (void)dispatch_all(h.opt.val_dtype, h.opt.accum_f64, h.opt.nrhs, false, [&](auto d) {
         sym = decltype(d)::mpk_symbol();
         return hipSuccess;
     });
@@ -865,7 +871,7 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.ctrl = plan->d_ctrl;
     a.watchdog = h.opt.watchdog_spins > 0 ? h.opt.watchdog_spins : (int64_t)1 << 24;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.nrhs, rec != nullptr, [&](auto d) {
+    hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.accum_f64, h.opt.nrhs, rec != nullptr, [&](auto d) {
         return decltype(d)::mpk(plan->workgroups, s, a, ra);
     });
     if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("mpk launch: ") + hipGetErrorString(e));
@@ -890,7 +896,7 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
         const double *x = q == 1 ? X : Y + (int64_t)(q - 2) * NK;
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
-        hipError_t e = dispatch_all(h.opt.val_dtype, K, rec != nullptr, [&](auto d) {
+        hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.accum_f64, K, rec != nullptr, [&](auto d) {
             return decltype(d)::spmv(blocks, s, reinterpret_cast<const int4 *>(plan->d_chunk), plan->d_rowptr,
                                      plan->d_col, plan->d_val, x, y,
                                      q, yq2, ra);
@@ -926,7 +932,7 @@ mpk_status mpk_run_sync(mpk_plan *plan, const double *X, double *Y, int32_t gran
     auto flush = [&]() -> mpk_status {
         const int blocks = L.n ? L.start[L.n] : 0;
         if (blocks > 0) {
-            hipError_t e = dispatch_all(h.opt.val_dtype, K, false, [&](auto d) {
+            hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.accum_f64, K, false, [&](auto d) {
                 return decltype(d)::seg(blocks, s, L, reinterpret_cast<const int4 *>(plan->d_chunk), plan->d_rowptr,
                                         plan->d_col, plan->d_val, X, Y, NK);
             });
@@ -986,6 +992,9 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     }
     mpk_status st = validate_csr(A);
     if (st != MPK_OK) return st;
+    if (o.val_dtype < MPK_F64 || o.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
+    if (o.accum_f64 != 0 && o.accum_f64 != 1) return fail(MPK_ERR_ARG, "accum_f64 must be 0 or 1");
+    if (o.reserved0 != 0 || o.reserved != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
     if (o.nrhs < 1 || o.nrhs > MPK_MAX_NRHS || !supported(o.val_dtype, o.nrhs, false))
         return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
     mpk_spmv *h = new (std::nothrow) mpk_spmv();
@@ -993,6 +1002,7 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     h->n = A->n;
     h->nnz = A->nnz;
     h->dtype = o.val_dtype;
+    h->acc64 = o.accum_f64;
     h->nrhs = o.nrhs;
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
@@ -1033,7 +1043,7 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
 static mpk_status spmv_launch(mpk_spmv *h, const double *x, double *y, hipStream_t s) {
     RecArgs ra;
     (void)fill_rec(nullptr, 1, h->nrhs, ra);
-    hipError_t e = dispatch_all(h->dtype, h->nrhs, false, [&](auto d) {
+    hipError_t e = dispatch_all(h->dtype, h->acc64, h->nrhs, false, [&](auto d) {
         return decltype(d)::spmv((int)h->nchunks, s, reinterpret_cast<const int4 *>(h->d_chunk), h->d_rowptr,
                                  h->d_col, h->d_val, x, y, 1,
                                  nullptr, ra);

@@ -602,8 +602,8 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
     if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
     if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
     if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
-    if (opt.reserved0 != 0 || opt.reserved[0] != 0 || opt.reserved[1] != 0)
-        return fail(MPK_ERR_ARG, "reserved option fields must be 0");
+    if (opt.reserved0 != 0 || opt.reserved != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
+    if (opt.accum_f64 != 0 && opt.accum_f64 != 1) return fail(MPK_ERR_ARG, "accum_f64 must be 0 or 1");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > MPK_MAX_SKEW) return fail(MPK_ERR_ARG, "skew must be in [1, 32]");
     if (opt.xcd_streams != 1 && opt.xcd_streams != 8) return fail(MPK_ERR_ARG, "xcd_streams must be 1 or 8");
@@ -931,8 +931,8 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.nrhs < 1 || opt.nrhs > MPK_MAX_NRHS) return fail(MPK_ERR_ARG, "nrhs must be in [1, 32]");
     if (opt.val_dtype < MPK_F64 || opt.val_dtype > MPK_BF16) return fail(MPK_ERR_ARG, "bad val_dtype");
     if (opt.root_mode < 0 || opt.root_mode > 1) return fail(MPK_ERR_ARG, "bad root_mode");
-    if (opt.reserved0 != 0 || opt.reserved[0] != 0 || opt.reserved[1] != 0)
-        return fail(MPK_ERR_ARG, "reserved option fields must be 0");
+    if (opt.reserved0 != 0 || opt.reserved != 0) return fail(MPK_ERR_ARG, "reserved option fields must be 0");
+    if (opt.accum_f64 != 0 && opt.accum_f64 != 1) return fail(MPK_ERR_ARG, "accum_f64 must be 0 or 1");
     if (opt.tile_nnz < 0 || opt.workgroups < 0) return fail(MPK_ERR_ARG, "negative launch option");
     if (opt.skew < 1 || opt.skew > MPK_MAX_SKEW) return fail(MPK_ERR_ARG, "skew must be in [1, 32]");
     if (opt.plan_on_device != 0 && opt.plan_on_device != 1) return fail(MPK_ERR_ARG, "plan_on_device must be 0 or 1");

@@ -208,6 +208,47 @@ def test_mixed_precision(dtype, u):
         assert np.all(np.abs(Y[q] - low[q]) <= c * bound[q])
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("baseline", [False, True])
+def test_mixed_precision_fp64_arithmetic(dtype, k, baseline):
+    # values stored as FP32 / BF16, products and sums in FP64: the FP64 oracle
+    # on the rounded values, to the FP64 bar (summation order only)
+    B, _ = W.stencil_27pt_random(16, seed=5)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (B.n, k)) if k > 1 else rng.uniform(-1, 1, B.n)
+    ref = O.spmv_powers(O.round_values(B, dtype), x, 5)
+    Y, pl = run_mpk(B, x, 5, 1 << 20, baseline=baseline, val_dtype=dtype, accum_f64=1, nrhs=k, tile_nnz=900,
+                    skew=2)
+    check_powers(Y.reshape(ref.shape), ref)
+    # FP32 arithmetic on the same storage is measurably further from it
+    Y32, _ = run_mpk(B, x, 5, 1 << 20, baseline=baseline, val_dtype=dtype, nrhs=k, tile_nnz=900, skew=2)
+    assert _rel_err(Y32.reshape(ref.shape)[4], ref[4]) > 1e-9
+
+
+def test_chebyshev_bf16_fp64_arithmetic():
+    # a Chebyshev step (complex state, recurrence epilogue) with BF16 storage
+    # and FP64 arithmetic equals the FP64 oracle on the rounded Hamiltonian
+    from paper_2205_01598_amd.cheb import ChebPropagator
+
+    dev = _dev()
+    A = W.anderson_3d(12, seed=4)
+    x = W.random_phase_state(A.n, seed=4)
+    M, p, r_dt = 32, 8, 10.0
+    ref = O.cheb_propagate(O.round_values(A, "bf16"), x, O.cheb_coefficients(M, r_dt))
+    pl = Plan(A, p, 1 << 20, nrhs=2, root_mode=1, tile_nnz=700, skew=2, val_dtype="bf16", accum_f64=1)
+    perm = pl.arrays()[0].astype(np.int64)
+    prop = ChebPropagator.schroedinger(pl, M, r_dt)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    for baseline in (False, True):
+        acc = torch.empty_like(X)
+        prop.step(X, acc, baseline=baseline)
+        pl.status()
+        h = np.empty((A.n, 2))
+        h[perm] = acc.cpu().numpy()
+        assert _rel_err(h, ref) <= 1e-12
+
+
 def test_recurrence_chebyshev_blocks():
     # degree-16 Chebyshev step as two MPK blocks of p = 8 with complex state
     dev = _dev()

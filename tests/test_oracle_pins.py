@@ -348,6 +348,40 @@ def test_lowp_rounding_rules():
     assert yf.tolist() == [float(np.float32(1 + 2.0 ** -8)), float(np.float32(1 + 3 * 2.0 ** -8)), 1.0]
 
 
+def test_round_values_nearest_even():
+    # the worked ties of the rounding rules, then brute force: the BF16 value
+    # is the nearer of the two BF16 neighbours of the FP32 value (ties to an
+    # even last kept bit), and the FP32 value is numpy's conversion
+    vals = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -30, -2.5, 0.0])
+    A = W.CSR(5, np.arange(6, dtype=np.int64), np.arange(5, dtype=np.int32), vals)
+    assert O.round_values(A, "bf16").val.tolist() == [1.0, 1 + 2.0 ** -6, 1.0, -2.5, 0.0]
+    rng = np.random.default_rng(7)
+    v = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-20, 20, 4000),
+                        (1 + (2 * rng.integers(0, 128, 500) + 1) * 2.0 ** -8) * 2.0 ** rng.integers(-10, 10, 500)])
+    n = len(v)
+    B = W.CSR(n, np.arange(n + 1, dtype=np.int64), np.zeros(n, dtype=np.int32), v)
+    f32 = O.round_values(B, "f32").val
+    assert np.array_equal(f32, v.astype(np.float32).astype(np.float64))
+    bf = O.round_values(B, "bf16").val
+    bits = f32.astype(np.float32).view(np.uint32)
+    lo = (bits & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    hi = ((bits & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    dlo, dhi = np.abs(f32 - lo), np.abs(hi - f32)
+    even_lo = ((bits >> np.uint32(16)) & np.uint32(1)) == 0
+    want = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(even_lo, lo, hi)))
+    assert np.array_equal(bf, want)
+    assert np.sum(dlo == dhi) >= 400  # the tie cases were exercised
+
+
+def test_round_values_matches_lowp_on_exact_data():
+    # small integers: every rounding and every FP32 sum is exact, so the
+    # FP32-arithmetic product and FP64 arithmetic on the rounded values agree
+    A = W.integer_stencil_27pt(6, seed=2)
+    x = np.random.default_rng(2).integers(-1, 2, A.n).astype(np.float64)
+    for dt in ("f32", "bf16"):
+        assert np.array_equal(O.spmv_powers(O.round_values(A, dt), x, 3), O.spmv_powers_lowp(A, x, 3, dt))
+
+
 def test_lowp_error_within_bound():
     A, _ = W.stencil_27pt_random(8, seed=1)
     x = W.uniform_vector(A.n, seed=1)

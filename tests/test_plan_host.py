@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from paper_2205_01598_amd import MpkError, Plan
+from paper_2205_01598_amd import MpkError, Plan, Spmv
 from paper_2205_01598_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -257,6 +257,12 @@ def test_plan_rejects_bad_input():
     for skew in (0, 33):
         with pytest.raises(MpkError, match="MPK_ERR_ARG"):
             Plan(A, 2, 1000, upload=False, skew=skew)
+    with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+        Plan(A, 2, 1000, upload=False, val_dtype="f32", accum_f64=2)
+    # the baseline handle validates before it touches the device
+    for kw in ({"val_dtype": 5}, {"accum_f64": 3}, {"reserved": 1}):
+        with pytest.raises(MpkError, match="MPK_ERR_ARG"):
+            Spmv(A, **kw)
     with pytest.raises(MpkError, match="MPK_ERR_UNSUPPORTED"):
         Plan(A, 2, 1000, upload=False, nrhs=4, val_dtype="bf16")
 
