@@ -597,6 +597,10 @@ def main():
         "per_call_timing": per_call,
         "baseline_ms": {k: round(v, 4) for k, v in base.items()},
         "baseline_gflops": round(flop / t_base / 1e6, 1),
+        # the bytes p SpMVs move (matrix p times), per MPK time, and the
+        # baseline's own rate: what the level blocking turns into speed
+        "effective_GBps_as_p_spmvs": {"mpk": round(p * spmv_bytes(n, nnz) / (ms * 1e-3) / 1e9, 1),
+                                      "baseline": round(p * spmv_bytes(n, nnz) / (t_base * 1e-3) / 1e9, 1)},
         "plan_seconds": round(plan_s, 2),
         "plan_spmv_equivalents": round(plan_s / (t_base / p * 1e-3), 0),
         "plan_seconds_plan_on_device": round(plan_dev_s, 2),
