@@ -148,3 +148,33 @@ def test_autotune_picks_fastest_and_leaves_plan_there():
     ref = O.spmv_powers(A, x, p)
     for q in range(p):
         assert np.linalg.norm(out[q] - ref[q]) <= 1e-12 * np.linalg.norm(ref[q])
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not os.path.exists(DB), reason="no sweep database")
+def test_learned_shortlist_tune_runs_its_best_measured_choice():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import workloads as W
+    from paper_2205_01598_amd import Plan
+
+    recs = tune.load_db(DB)
+    train, _ = tune.split_seeds(recs)
+    tuner = tune.LearnedTuner(hidden=16, seed=1)
+    tuner.fit(train, steps=200)  # a rough model is enough to exercise the path
+    A = W.stencil_2d(120, 5)
+    p = 4
+    pl = Plan(A, p, 256 << 20, root_mode=1)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(W.uniform_vector(A.n, seed=0)[perm])).cuda()
+    Y = torch.empty((p, A.n), dtype=torch.float64, device="cuda")
+    tune._apply(pl, p, tune.DEFAULT)
+    short = tuner.shortlist(tune.plan_features(pl), 3)
+    cfg, ms, timings = tuner.tune(torch, pl, p, lambda: pl.run(X, Y), m=3, reps=2, warmup=1)
+    assert [c for c, _ in timings] == short and cfg in short
+    assert ms == min(t for _, t in timings)
+    fresh = Plan(A, p, int(cfg["cache_mb"]) << 20, upload=False, root_mode=1,
+                 **{k: int(v) for k, v in cfg.items() if k != "cache_mb"})
+    for a, b in zip(pl.tiles(), fresh.tiles()):
+        assert np.array_equal(a, b)
