@@ -5,7 +5,7 @@ import numpy as np
 
 import workloads as W
 
-N_CASES = 32
+N_CASES = 40
 
 
 def case(seed):
@@ -37,4 +37,9 @@ def case(seed):
     if seed >= 24:
         # large ticket skews (drawn last, so the cases below 24 are unchanged)
         opts["skew"] = int(rng.choice([4, 8, 16, 32]))
+    if seed >= 32 and rec == 0 and k <= 2:
+        # FP32 / BF16 storage with FP64 arithmetic: the FP64 oracle on the
+        # rounded values keeps the FP64 bar
+        opts["val_dtype"] = str(rng.choice(["f32", "bf16"]))
+        opts["accum_f64"] = 1
     return A, p, C, opts, x

@@ -1,8 +1,9 @@
 """GPU parity sweep over seeded random configurations (fuzz_cases: random
 irregular, banded, 2D stencil and power-law matrices; random p, cache
 budget, tiles, skew, ticket streams, grid size, right-hand sides and
-recursion stages) against the oracle, FP64, relative error <= 1e-12 per
-power.  test_plan_fuzz checks the same plans on the host."""
+recursion stages, FP32 / BF16 storage with FP64 arithmetic) against the
+oracle (on the rounded values where the storage rounds them), relative
+error <= 1e-12 per power.  test_plan_fuzz checks the same plans on the host."""
 import numpy as np
 import pytest
 
@@ -30,7 +31,8 @@ def test_fuzz_parity(seed):
     pl.status()
     out = np.empty((p,) + x.shape)
     out[:, perm] = Y.cpu().numpy().reshape((p,) + x.shape)
-    ref = O.spmv_powers(A, x, p)
+    dt = opts.get("val_dtype", "f64")
+    ref = O.spmv_powers(A if dt == "f64" else O.round_values(A, dt), x, p)
     for q in range(p):
         nb = np.linalg.norm(ref[q])
         e = np.linalg.norm(out[q] - ref[q]) / (nb if nb > 0 else 1.0)

@@ -19,7 +19,8 @@ def test_fuzz_plan(seed):
     stages = opts.pop("recursion_stages")
     if stages == 0:
         root_mode = opts.pop("root_mode")
-        _check_plan(A, p, C, root_mode, **opts)
+        opts.pop("accum_f64", None)
+        _check_plan(A, p, C, root_mode, dtype=opts.pop("val_dtype", "f64"), **opts)
     else:
         pl = Plan(A, p, C, upload=False, recursion_stages=stages, **opts)
         operm, olp = O.bfs_levels(A, opts["root_mode"])
