@@ -10,12 +10,14 @@ One step = one call of the hot path: mpk_run computing y_1..y_p.  Reported:
 MPK GFLOP/s (2 nnz p / t), speedup over the faster of two tuned baselines
 (p SpMV launches on the matrix as given, and on the BFS-renumbered matrix),
 roofline fraction of the persistent kernel against 8 TB/s HBM on algorithmic
-bytes, mixed-precision (FP32 / BF16 values) throughput and error against the
-FP64 run, the synchronisation ladder, refined plans (recursion, s_m = 1, 2),
-and the FP64 CPU oracle timed on the
-host (the only use of the oracle here).  Other workloads: 64^2 Laplacian,
-Anderson 128^3 and heat-equation 160^3 Chebyshev propagation, multi-RHS RGG,
-the learned tuner.
+bytes, mixed-precision (FP32 / BF16 values, FP32 or FP64 arithmetic)
+throughput and error against the FP64 run, the synchronisation ladder,
+refined plans (recursion, s_m = 1, 2) and bulky-level matrices, and the FP64
+CPU oracle timed on the host (the only use of the oracle here).  Every MPK
+configuration reported is the autotuner's pick among a few candidates.
+Other workloads: 64^2 Laplacian, Anderson 128^3 and heat-equation 160^3
+Chebyshev propagation, multi-RHS RGG, a thin-level 2D 9-point 4096^2
+stencil, the learned tuner.
 """
 from __future__ import annotations
 
