@@ -374,9 +374,19 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="only the headline p (no p=4/6)")
     ap.add_argument("--probe", action="store_true",
                     help="load-only bandwidth versus footprint (one full pass per launch) and exit")
+    ap.add_argument("--thin-levels-only", action="store_true",
+                    help="only the thin-level 2D 9-point 4096^2 workload (for profiling); prints its JSON and exits")
     args = ap.parse_args()
     if args.probe:
         probe()
+        return
+    if args.thin_levels_only:
+        import torch
+
+        import workloads as W
+        from paper_2205_01598_amd import Plan
+
+        print(json.dumps(bench_thin_levels(torch, Plan, W, torch.device("cuda:0"))), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
