@@ -9,9 +9,10 @@
  *     (Sec. 3);
  *   - preprocessing takes A, p_m and a cache budget C, levels the graph of A
  *     by breadth-first search (Eq. 3), renumbers it level by level (Sec. 4.1),
- *     merges consecutive levels into level groups under Eq. (5) (Sec. 4.3)
- *     and orders the (group, power) nodes by the diagonals of the Lp diagram
- *     (Sec. 4.2, Fig. 6);
+ *     merges consecutive levels into level groups under Eq. (5) (Sec. 4.3),
+ *     optionally refines bulky groups recursively (Sec. 4.4), and orders the
+ *     (group, power) nodes by the diagonals of the Lp diagram (Sec. 4.2,
+ *     Fig. 6) or by skewed diagonals (mpk_options.skew);
  *   - execution runs the powers over that order with point-to-point
  *     dependencies instead of barriers (Sec. 4.3, "p2p").
  * The baseline is p_m back-to-back SpMVs (Sec. 3.1, Fig. 2).
