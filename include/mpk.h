@@ -55,7 +55,7 @@ enum {
     MPK_ERR_OOM = -3,          /* host or device allocation failed */
     MPK_ERR_HIP = -4,          /* a HIP runtime call failed */
     MPK_ERR_TIMEOUT = -5,      /* a device dependency wait exceeded the watchdog */
-    MPK_ERR_UNSUPPORTED = -6,  /* valid request this build does not handle (e.g. nnz >= 2^31) */
+    MPK_ERR_UNSUPPORTED = -6,  /* valid request the library does not handle (e.g. nnz >= 2^31) */
     MPK_ERR_STATE = -7         /* call out of order (e.g. run before upload) */
 };
 

@@ -3,8 +3,8 @@
 * ``sweep``: for each matrix of a seeded corpus, one plan (one BFS), then every
   launch configuration of ``config_grid()`` through ``mpk_plan_retune`` and a
   timed ``mpk_run``; one JSON record per (matrix, p, configuration) appended
-  to a timing database.  The exhaustive sweep is the fallback and the judge
-  of the learned choice.
+  to a timing database.  The exhaustive sweep is the fallback of the learned
+  choice and the yardstick it is measured against.
 * ``DeviceMLP``: the 3-layer perceptron whose forward pass, backward pass and
   Adam update are the library's HIP kernels (``mpk_mlp_*``); PyTorch only
   holds the device buffers.
