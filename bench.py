@@ -289,21 +289,66 @@ def bench_thin_levels(torch, Plan, W, dev):
 
 
 def probe():
-    """Load-only read bandwidth versus footprint: L2 (4 MB per XCD), the
-    256 MB Infinity Cache and HBM (the analog of the paper's Fig. 1)."""
+    """Memory-hierarchy probes (the analog of the paper's Fig. 1, Sec. 2):
+    load-only read rate against footprint for the L2 (4 MB per XCD), the
+    256 MB Infinity Cache and HBM, with 1-8 loads in flight per thread and
+    whole-buffer or per-XCD parts; the XCD placement of workgroups; and the
+    latency of a flag hop between two workgroups at agent and at workgroup
+    scope.  Prints a text report and one JSON line."""
     import torch
 
     from paper_2205_01598_amd import bw_probe
+    from paper_2205_01598_amd.mpk import hop_probe, xcd_ids
 
     dev = torch.device("cuda:0")
+    report = {}
+    # ---- XCD placement ------------------------------------------------------------
+    place = {}
+    for wg, spin in ((64, 0), (1024, 0), (2048, 0), (1024, 2000), (2048, 2000), (8192, 200)):
+        ids = torch.full((wg,), -1, dtype=torch.int32, device=dev)
+        xcd_ids(ids, wg, spin)
+        h = ids.cpu().numpy()
+        exp = np.arange(wg) % 8
+        place[f"wg{wg}_spin{spin}"] = {"mismatch": int((h != exp).sum()),
+                                       "per_xcd": np.bincount(h[h >= 0], minlength=8).tolist()}
+    report["xcd_placement"] = place
+    print(f"XCD placement (mismatches against b % 8): {place}", flush=True)
+    # ---- flag hop latency ---------------------------------------------------------------
+    flags = torch.zeros(64, dtype=torch.int32, device=dev)
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    hops = {}
+    for name, peer, scope in (("agent_scope_other_xcd", 1, 0), ("agent_scope_same_xcd", 8, 0),
+                              ("workgroup_scope_same_xcd", 8, 1)):
+        vals = []
+        for _ in range(3):
+            wall_khz = hop_probe(flags, peer, scope, 2000, 1 << 20, out)
+            ticks, done = (int(t) for t in out.cpu().numpy())
+            vals.append((ticks, done))
+        best = min(t for t, d in vals if d == 2000) if all(d == 2000 for _, d in vals) else None
+        hops[name] = {"one_way_ns": round(best / 4000 / wall_khz * 1e6, 1) if best else None,
+                      "completed": [d for _, d in vals]}
+    report["flag_hop"] = hops
+    print(f"flag hop latency (one way): {hops}", flush=True)
+    # ---- read rate against footprint ----------------------------------------------------
     buf = torch.empty(4 << 30, dtype=torch.uint8, device=dev).fill_(1)
     sink = torch.zeros(1, dtype=torch.float64, device=dev)
-    print("footprint_MB  GB/s(one pass per launch, 8192 WGs)  GB/s(each WG re-reads its share 16x, 2048 WGs)")
-    for mb in (8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 512, 1024, 2048, 4096):
+    modes = [("pass_u1_wg8192", 1, 8192, 1, False), ("pass_u4_wg2048", 4, 2048, 1, False),
+             ("reread_u4_wg2048", 4, 2048, 1, True), ("reread_parts8_u4_wg2048", 4, 2048, 8, True),
+             ("reread_parts8_u8_wg4096", 8, 4096, 8, True), ("reread_parts8_u2_wg8192", 2, 8192, 8, True)]
+    rows = {}
+    print("footprint_MB " + " ".join(f"{m[0]:>24s}" for m in modes) + "   (GB/s)", flush=True)
+    for mb in (8, 16, 32, 48, 64, 96, 128, 160, 192, 256, 384, 512, 1024, 2048, 4096):
         b = buf[: mb << 20]
-        t1 = timed(torch, lambda: bw_probe(b, 1, 8192, sink), 20, 3)
-        t2 = timed(torch, lambda: bw_probe(b, 16, 2048, sink), 5, 1)
-        print(f"{mb:8d}  {mb * (1 << 20) / t1 / 1e6:12.1f}  {16 * mb * (1 << 20) / t2 / 1e6:12.1f}", flush=True)
+        line = {}
+        for name, u, wg, parts, reread in modes:
+            reps = max(1, (2048 // mb)) if reread else 1
+            launches = 20 if not reread else 5
+            t = timed(torch, lambda: bw_probe(b, reps, wg, sink, loads_per_thread=u, parts=parts), launches, 2)
+            line[name] = round(reps * mb * (1 << 20) / t / 1e6, 1)
+        rows[mb] = line
+        print(f"{mb:10d} " + " ".join(f"{line[m[0]]:24.1f}" for m in modes), flush=True)
+    report["read_GBps"] = rows
+    print(json.dumps(report), flush=True)
 
 
 def bench_learned_tuner(torch, plan, X, Y, p, log):

@@ -339,6 +339,39 @@ void spmv_destroy(mpk_spmv *h);
 mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups,
                         double *sink, void *stream);
 
+/* The same probe with `loads_per_thread` (1, 2, 4 or 8) independent 16-byte
+ * loads per thread in flight and the buffer cut into `parts` (1 or 8) equal
+ * contiguous parts: workgroup b reads part b % parts only.  On MI355X the
+ * workgroups b, b + 8, ... of a launch run on one XCD, so with parts = 8 each
+ * XCD re-reads its own part: a part larger than the XCD's 4 MB L2 inside a
+ * buffer smaller than the 256 MB Infinity Cache measures the Infinity Cache
+ * (the memory hierarchy levels of Sec. 2, Fig. 1).  bytes must be a multiple
+ * of 16*parts, buf 16-byte aligned (device), workgroups >= parts. */
+mpk_status mpk_bw_probe_ex(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups,
+                           int32_t loads_per_thread, int32_t parts, double *sink, void *stream);
+
+/* XCD placement: ids[b] (device, `workgroups` int32) receives the hardware
+ * XCD index (XCC_ID register) of workgroup b of a launch of `workgroups`
+ * 256-thread workgroups, each of which then sleeps `spin` rounds so that the
+ * later ones are placed while the earlier ones still run.  The XCD-sliced
+ * ticket streams (mpk_options.xcd_streams = 8) assume ids[b] = b % 8. */
+mpk_status mpk_xcd_ids(int32_t *ids, int32_t workgroups, int64_t spin, void *stream);
+
+/* Latency of a point-to-point dependency hop (Sec. 4.3 replaces barriers by
+ * such hops): workgroups 0 and `peer` (1..255) of one launch pass a counter
+ * back and forth through two flags in `flags` (device, 64 uint32, cleared by
+ * the call), `iters` round trips.  scope 0: agent-scope flag stores and
+ * loads (the device-coherent level, as mpk_run uses them); scope 1:
+ * workgroup-scope stores and loads, which bypass the L1 and meet in the L2
+ * of one XCD (peer = 8 shares workgroup 0's XCD; with another XCD they never
+ * meet).  Every poll gives up after max_polls reads.  out (device, 2
+ * uint64): elapsed wall-clock ticks of workgroup 0 and the round trips
+ * completed (iters unless a poll gave up); wall_clock_khz (host, may be NULL)
+ * receives the tick rate.  The flags are cleared with a memset on `stream`,
+ * so the call is not meant for stream capture. */
+mpk_status mpk_hop_probe(uint32_t *flags, int32_t peer, int32_t scope, int32_t iters, int64_t max_polls,
+                         uint64_t *out, int32_t *wall_clock_khz, void *stream);
+
 /* ---- learned tuner: a 3-layer perceptron, FP32, on the device -------------
  * out = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with D inputs and H hidden
  * units (H <= 256).  Parameters are one float array laid out W1[H][D], b1[H],

@@ -99,6 +99,11 @@ SIGNATURES = {
     "spmv_powers_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
     "spmv_destroy": (None, [_P]),
     "mpk_bw_probe": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "mpk_bw_probe_ex": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, _P, _P]),
+    "mpk_xcd_ids": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int64, _P]),
+    "mpk_hop_probe": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P,
+                                       _I32P, _P]),
     "mpk_mlp_param_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32]),
     "mpk_mlp_forward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]),
     "mpk_mlp_backward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P,

@@ -435,6 +435,89 @@ __global__ __launch_bounds__(kBlock) void bw_probe(const double2 *__restrict__ b
     if ((threadIdx.x & 63) == 0 && acc == 12345.678) sink[0] = acc;  // keeps the loads alive
 }
 
+// The same probe with U independent 16-byte loads per thread in flight and an
+// optional split of the buffer into `parts` contiguous parts: workgroup b
+// reads part b % parts only, striding over it with the other workgroups of
+// that part.  With parts = 8 every XCD re-reads its own part (workgroups
+// b, b + 8, ... share an XCD), so a part larger than an XCD's L2 but a buffer
+// smaller than the Infinity Cache measures the Infinity Cache read rate.
+template <int U>
+__global__ __launch_bounds__(kBlock) void bw_probe_ex(const double2 *__restrict__ buf, int64_t n2, int parts, int reps,
+                                                      double *sink) {
+    const int part = blockIdx.x % parts;
+    const int64_t j = blockIdx.x / parts;
+    const int64_t cnt = (gridDim.x - part + parts - 1) / parts;
+    const double2 *b = buf + (int64_t)part * n2;
+    const int64_t step = cnt * kBlock * U;
+    double acc = 0.0;
+    for (int rep = 0; rep < reps; ++rep) {
+        for (int64_t base = j * kBlock * U + threadIdx.x; base < n2; base += step) {
+            double2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = base + (int64_t)u * kBlock;
+                v[u] = i < n2 ? b[i] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += v[u].x + v[u].y;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0 && acc == 12345.678) sink[0] = acc;
+}
+
+// XCD (accelerator complex die) running the calling wavefront: bits [3:0] of
+// the XCC_ID hardware register (hwreg 20 on CDNA3/CDNA4).
+__device__ __forceinline__ int hw_xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15; }
+
+// Records the XCD of every workgroup; each workgroup then sleeps `spin`
+// rounds so that later workgroups are placed while earlier ones still hold
+// their slots (the situation of a persistent grid).
+__global__ __launch_bounds__(kBlock) void xcd_ids_kernel(int32_t *ids, int64_t spin) {
+    if (threadIdx.x == 0) ids[blockIdx.x] = hw_xcc_id();
+    for (int64_t i = 0; i < spin; ++i) __builtin_amdgcn_s_sleep(16);
+}
+
+// Dependency-hop latency: two workgroups (blockIdx 0 and `peer`) pass a
+// counter back and forth through two flags, `iters` round trips.  scope 0:
+// agent-scope flag stores and loads (written through to the device-coherent
+// level, read past the L2); scope 1: workgroup-scope stores and loads (L1
+// bypassed, served by the L2 of the XCD; correct only when both workgroups
+// share an XCD).  Every poll is bounded by `max_polls`; out[0] = elapsed
+// wall-clock ticks of workgroup 0, out[1] = completed round trips.
+__global__ void hop_probe_kernel(uint32_t *flags, int peer, int scope, int iters, int64_t max_polls,
+                                 uint64_t *out) {
+    const int b = blockIdx.x;
+    if ((b != 0 && b != peer) || threadIdx.x != 0) return;
+    const bool ping = b == 0;
+    uint32_t *mine = flags + (ping ? 0 : 32), *theirs = flags + (ping ? 32 : 0);
+    auto st = [&](uint32_t *p, uint32_t v) {
+        if (scope == 0)
+            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto ld = [&](uint32_t *p) -> uint32_t {
+        return scope == 0 ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    const uint64_t t0 = wall_clock64();
+    int done = 0;
+    for (int i = 1; i <= iters; ++i) {
+        if (ping) st(mine, (uint32_t)i);
+        int64_t polls = 0;
+        while (ld(theirs) != (uint32_t)i && ++polls < max_polls) {
+        }
+        if (polls >= max_polls) break;
+        if (!ping) st(mine, (uint32_t)i);
+        done = i;
+    }
+    if (ping) {
+        out[0] = wall_clock64() - t0;
+        out[1] = (uint64_t)done;
+    }
+}
+
 // ----------------------------------------------------------------------------
 // launch dispatch: value type x right-hand sides K x recurrence
 // ----------------------------------------------------------------------------
@@ -1087,6 +1170,53 @@ mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t w
     if (reps < 1 || workgroups < 1) return fail(MPK_ERR_ARG, "reps and workgroups must be >= 1");
     hipLaunchKernelGGL(bw_probe, dim3(workgroups), dim3(kBlock), 0, reinterpret_cast<hipStream_t>(stream),
                        reinterpret_cast<const double2 *>(buf), (int64_t)(bytes / 16), reps, sink);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status mpk_bw_probe_ex(const void *buf, uint64_t bytes, int32_t reps, int32_t workgroups,
+                           int32_t loads_per_thread, int32_t parts, double *sink, void *stream) {
+    if (!buf || !sink) return fail(MPK_ERR_ARG, "null pointer");
+    if ((uintptr_t)buf % 16) return fail(MPK_ERR_ARG, "buffer must be 16-byte aligned");
+    if (parts != 1 && parts != 8) return fail(MPK_ERR_ARG, "parts must be 1 or 8");
+    if (bytes == 0 || bytes % (16u * (uint64_t)parts)) return fail(MPK_ERR_ARG, "bytes must be a multiple of 16*parts");
+    if (reps < 1 || workgroups < parts) return fail(MPK_ERR_ARG, "reps >= 1 and workgroups >= parts required");
+    const int64_t n2 = (int64_t)(bytes / 16 / (uint64_t)parts);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const double2 *b = reinterpret_cast<const double2 *>(buf);
+    switch (loads_per_thread) {
+        case 1: hipLaunchKernelGGL(bw_probe_ex<1>, dim3(workgroups), dim3(kBlock), 0, s, b, n2, parts, reps, sink); break;
+        case 2: hipLaunchKernelGGL(bw_probe_ex<2>, dim3(workgroups), dim3(kBlock), 0, s, b, n2, parts, reps, sink); break;
+        case 4: hipLaunchKernelGGL(bw_probe_ex<4>, dim3(workgroups), dim3(kBlock), 0, s, b, n2, parts, reps, sink); break;
+        case 8: hipLaunchKernelGGL(bw_probe_ex<8>, dim3(workgroups), dim3(kBlock), 0, s, b, n2, parts, reps, sink); break;
+        default: return fail(MPK_ERR_ARG, "loads_per_thread must be 1, 2, 4 or 8");
+    }
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status mpk_xcd_ids(int32_t *ids, int32_t workgroups, int64_t spin, void *stream) {
+    if (!ids) return fail(MPK_ERR_ARG, "null pointer");
+    if (workgroups < 1 || spin < 0) return fail(MPK_ERR_ARG, "workgroups >= 1 and spin >= 0 required");
+    hipLaunchKernelGGL(xcd_ids_kernel, dim3(workgroups), dim3(kBlock), 0, reinterpret_cast<hipStream_t>(stream), ids,
+                       spin);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status mpk_hop_probe(uint32_t *flags, int32_t peer, int32_t scope, int32_t iters, int64_t max_polls,
+                         uint64_t *out, int32_t *wall_clock_khz, void *stream) {
+    if (!flags || !out) return fail(MPK_ERR_ARG, "null pointer");
+    if (wall_clock_khz) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(wall_clock_khz, hipDeviceAttributeWallClockRate, dev));
+    }
+    if (peer < 1 || peer > 255 || (scope != 0 && scope != 1) || iters < 1 || max_polls < 1)
+        return fail(MPK_ERR_ARG, "peer in [1, 255], scope 0 or 1, iters >= 1 and max_polls >= 1 required");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemsetAsync(flags, 0, 64 * sizeof(uint32_t), s));
+    hipLaunchKernelGGL(hop_probe_kernel, dim3(peer + 1), dim3(64), 0, s, flags, peer, scope, iters, max_polls, out);
     HIP_TRY(hipGetLastError());
     return MPK_OK;
 }

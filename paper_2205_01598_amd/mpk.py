@@ -214,7 +214,30 @@ class Spmv:
         return Y
 
 
-def bw_probe(buf, reps: int, workgroups: int, sink, stream=None):
+def bw_probe(buf, reps: int, workgroups: int, sink, stream=None, loads_per_thread: int = 0, parts: int = 1):
+    """Load-only read probe over the whole tensor ``buf``; loads_per_thread
+    > 0 selects ``mpk_bw_probe_ex`` (that many loads in flight per thread,
+    buffer cut into ``parts`` per-XCD parts)."""
     nbytes = buf.numel() * buf.element_size()
-    check(lib().mpk_bw_probe(_ptr(buf), int(nbytes), int(reps), int(workgroups), _ptr(sink),
-                             _stream(stream)))
+    if loads_per_thread:
+        check(lib().mpk_bw_probe_ex(_ptr(buf), int(nbytes), int(reps), int(workgroups), int(loads_per_thread),
+                                    int(parts), _ptr(sink), _stream(stream)))
+    else:
+        check(lib().mpk_bw_probe(_ptr(buf), int(nbytes), int(reps), int(workgroups), _ptr(sink),
+                                 _stream(stream)))
+
+
+def xcd_ids(ids, workgroups: int, spin: int = 0, stream=None):
+    """Hardware XCD of every workgroup of a launch (``mpk_xcd_ids``) into the
+    int32 device tensor ``ids``."""
+    check(lib().mpk_xcd_ids(_ptr(ids), int(workgroups), int(spin), _stream(stream)))
+    return ids
+
+
+def hop_probe(flags, peer: int, scope: int, iters: int, max_polls: int, out, stream=None):
+    """Round trips of a flag between workgroups 0 and ``peer`` (``mpk_hop_probe``)
+    into ``out``; returns the wall-clock tick rate in kHz."""
+    khz = ctypes.c_int32(0)
+    check(lib().mpk_hop_probe(_ptr(flags), int(peer), int(scope), int(iters), int(max_polls), _ptr(out),
+                              ctypes.byref(khz), _stream(stream)))
+    return khz.value
