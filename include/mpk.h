@@ -208,7 +208,12 @@ mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
  * left as it was. */
 mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, const mpk_options *opt);
 
-/* Summary of a plan.  info: host, written on success. */
+/* Summary of a plan: the sizes of the preprocessing results of Sec. 4 -
+ * levels L (Eq. 3), level groups (Eq. 5; violating_groups counts the bulky
+ * single levels of Sec. 4.4), the Lp nodes G*p of Fig. 6 as device tiles and
+ * tickets - and the timing of each preprocessing phase (Sec. 6 reports the
+ * preprocessing cost).  info: host, written on success; MPK_ERR_ARG for a
+ * null argument. */
 mpk_status mpk_plan_query(const mpk_plan *plan, mpk_plan_info *info);
 
 /* Host copies of the plan arrays.  Any pointer may be NULL to skip it.
@@ -276,14 +281,18 @@ mpk_status mpk_plan_features(const mpk_plan *plan, double *features);
 mpk_status mpk_plan_upload(mpk_plan *plan);
 
 /* Gather/scatter between the original and the plan numbering (N x k FP64,
- * device).  to_plan = 1: out[i] = in[perm[i]]; to_plan = 0: out[perm[i]] =
- * in[i].  in and out must not alias. */
+ * device), with the permutation vector of Sec. 4.1 (the renumbering that
+ * lists the levels one after the other; the paper's MPK then runs on the
+ * permuted matrix and vectors, Sec. 4.1 and the RACE paragraph of Sec. 4).
+ * to_plan = 1: out[i] = in[perm[i]]; to_plan = 0: out[perm[i]] = in[i].
+ * in and out must not alias (MPK_ERR_ARG); MPK_ERR_STATE before upload. */
 mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int32_t k,
                        int32_t to_plan, void *stream);
 
 /* One level-blocked MPK run (Sec. 4.2-4.3) in plan numbering: X (device,
  * N x k, read only) holds y_0; Y (device, p x N x k) receives y_1..y_p.  Y
- * must not overlap X, y_prev or acc.  rec = NULL gives plain powers.
+ * must not overlap X, y_prev or acc, and acc must not overlap X or y_prev
+ * (MPK_ERR_ARG otherwise).  rec = NULL gives plain powers.
  * k is the plan's nrhs.  Asynchronous; a dependency wait that outlives the
  * watchdog makes the kernel stop early and is reported by mpk_plan_status.
  * Runs of one plan must not overlap (its flags and counters are shared).
@@ -293,10 +302,23 @@ mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int3
 mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec,
                    void *stream);
 
+/* mpk_run limited to the first `powers` powers (1 <= powers <= the plan's
+ * p): y_1..y_powers into Y (device, powers x N x k), the recurrence arrays
+ * read for powers entries (2*powers for complex coef).  Sec. 5 runs a power
+ * count that is not a multiple of p_m as blocks of p_m followed by one
+ * shorter block; this is that block, on the same plan: the tickets of the
+ * higher powers are skipped (nothing waits for them).  Same buffer rules and
+ * errors as mpk_run, plus MPK_ERR_ARG for powers out of range. */
+mpk_status mpk_run_first(mpk_plan *plan, int32_t powers, const double *X, double *Y,
+                         const mpk_recurrence *rec, void *stream);
+
 /* Baseline on the renumbered matrix: p back-to-back SpMV launches (Fig. 2)
  * over the plan's device matrix, same arguments and results as mpk_run. */
 mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y,
                             const mpk_recurrence *rec, void *stream);
+/* The baseline limited to the first `powers` powers (powers SpMV launches). */
+mpk_status mpk_run_baseline_first(mpk_plan *plan, int32_t powers, const double *X, double *Y,
+                                  const mpk_recurrence *rec, void *stream);
 
 /* Level-blocked MPK with bulk synchronisation instead of point-to-point
  * flags (the variants Sec. 4.2 starts from before Sec. 4.3 replaces the

@@ -8,6 +8,11 @@
  *                        (the baseline MPK of Sec. 3.1, Fig. 2), which is the
  *                        plain definition of what any MPK computes:
  *                        y_p = A^p x for p = 1..p_m, every y_p kept.
+ *   orc_spmv_powers_omp  the same loops with the rows of each SpMV shared
+ *                        among OpenMP threads, schedule(static), as the
+ *                        paper's baseline runs them (Sec. 3.1, Sec. 6).  A row
+ *                        is still summed by one thread in stored order, so the
+ *                        result equals orc_spmv_powers bit for bit.
  *   orc_round_values     matrix values rounded to FP32 / BF16 storage, as FP64
  *                        (with orc_spmv_powers: the FP64-arithmetic variant)
  *   orc_spmv_powers_lowp the same with matrix values and inputs rounded to a
@@ -61,6 +66,27 @@ int orc_spmv_powers(int64_t n, const int64_t *rowptr, const int32_t *col,
     return 0;
 }
 
+int orc_spmv_powers_omp(int64_t n, const int64_t *rowptr, const int32_t *col,
+                        const double *val, int32_t k, int32_t p,
+                        const double *x, double *y, int32_t threads)
+{
+    if (n < 0 || k < 1 || p < 1 || threads < 1) return -1;
+    for (int32_t q = 1; q <= p; ++q) {
+        const double *in = (q == 1) ? x : y + (int64_t)(q - 2) * n * k;
+        double *out = y + (int64_t)(q - 1) * n * k;
+#pragma omp parallel for schedule(static) num_threads(threads)
+        for (int64_t r = 0; r < n; ++r) {
+            for (int32_t c = 0; c < k; ++c) {
+                double tmp = 0.0;
+                for (int64_t j = rowptr[r]; j < rowptr[r + 1]; ++j)
+                    tmp += val[j] * in[(int64_t)col[j] * k + c];
+                out[r * k + c] = tmp;
+            }
+        }
+    }
+    return 0;
+}
+
 /* Round a double to float with round-to-nearest-even (the C cast does that). */
 static float to_f32(double v) { return (float)v; }
 
@@ -84,10 +110,9 @@ static float to_bf16(float f)
 /*
  * Mixed-precision powers.  Matrix values: vdtype 1 = f64 -> f32 (RNE),
  * vdtype 2 = f64 -> f32 -> bf16 (RNE at each step).  Each power:
- *   x_f32 = round_f32(y_{q-1}),  s = sum_j a_j * x_f32[col_j]  (f32 FMA-free
- *   multiply then add, stored order),  y_q = (double)s.
- * The GPU path uses fused multiply-adds and another summation order, so the
- * two agree to f32 rounding, not bit for bit.
+ *   x_f32 = round_f32(y_{q-1}),  s = sum_j a_j * x_f32[col_j]  (every
+ *   product rounded to f32, then added to an f32 running sum that starts at
+ *   0, in stored order; no fused multiply-add),  y_q = (double)s.
  */
 /* Matrix values as a lower-precision storage holds them, widened back to
  * FP64: vdtype 1 = FP32 (round to nearest even), 2 = BF16 (FP32 first, then

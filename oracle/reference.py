@@ -11,7 +11,12 @@ Functions and the passages they follow
                      for p = 1..p_m and stores every y_p; the baseline is p_m
                      back-to-back CRS SpMVs.  This is the exact target every
                      MPK variant must reproduce (level blocking only reorders
-                     these operations, Sec. 4.2).
+                     these operations, Sec. 4.2).  threads > 1 shares the rows
+                     of every SpMV among OpenMP threads (static schedule, the
+                     paper's baseline, Sec. 6); each row is still summed in
+                     stored order, so the result is the same bit for bit.
+  permute_symmetric  P A P^T of the Sec. 4.1 renumbering (the permuted
+                     matrix the MPK runs on).
   round_values       values as FP32 / BF16 storage holds them, as FP64; with
                      spmv_powers the FP64-arithmetic mixed-precision variant
   spmv_powers_lowp   the same product with matrix values stored in FP32 or
@@ -56,6 +61,9 @@ def _load():
     lib.orc_spmv_powers.restype = ctypes.c_int
     lib.orc_spmv_powers.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
                                     ctypes.c_int32, _f64p, _f64p]
+    lib.orc_spmv_powers_omp.restype = ctypes.c_int
+    lib.orc_spmv_powers_omp.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
+                                        ctypes.c_int32, _f64p, _f64p, ctypes.c_int32]
     lib.orc_spmv_powers_lowp.restype = ctypes.c_int
     lib.orc_spmv_powers_lowp.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]
@@ -86,18 +94,24 @@ def _p(a, t):
 # powers
 # ----------------------------------------------------------------------------
 
-def spmv_powers(A, x, p: int) -> np.ndarray:
+def spmv_powers(A, x, p: int, threads: int = 1) -> np.ndarray:
     """y_q = A y_{q-1}, y_0 = x, for q = 1..p (Sec. 3.1, Fig. 2), FP64.
 
     ``x`` has shape (n,) or (n, k) (k right-hand sides, row-major).  Returns an
-    array of shape (p, n) or (p, n, k) holding y_1..y_p.
+    array of shape (p, n) or (p, n, k) holding y_1..y_p.  ``threads`` > 1
+    runs the rows of each SpMV on that many OpenMP threads with the same
+    per-row arithmetic (identical result).
     """
     rowptr, col, val = _arrs(A)
     x = np.ascontiguousarray(x, dtype=np.float64)
     k = 1 if x.ndim == 1 else x.shape[1]
     y = np.empty((p, A.n * k), dtype=np.float64)
-    rc = _load().orc_spmv_powers(A.n, _p(rowptr, _i64p), _p(col, _i32p), _p(val, _f64p),
-                                 k, p, _p(x, _f64p), _p(y, _f64p))
+    if threads > 1:
+        rc = _load().orc_spmv_powers_omp(A.n, _p(rowptr, _i64p), _p(col, _i32p), _p(val, _f64p),
+                                         k, p, _p(x, _f64p), _p(y, _f64p), int(threads))
+    else:
+        rc = _load().orc_spmv_powers(A.n, _p(rowptr, _i64p), _p(col, _i32p), _p(val, _f64p),
+                                     k, p, _p(x, _f64p), _p(y, _f64p))
     if rc != 0:
         raise ValueError("orc_spmv_powers failed")
     return y.reshape((p, A.n) if x.ndim == 1 else (p, A.n, k))
@@ -227,23 +241,21 @@ def lp_schedule(G: int, p: int) -> np.ndarray:
 
 
 def permute_symmetric(A, perm):
-    """P A P^T with perm[new] = old, columns ascending in the new numbering."""
+    """P A P^T with perm[new] = old (Sec. 4.1): entry (i, j) of the result is
+    A[perm[i], perm[j]].  Every stored entry (r, c, v) of A moves to
+    (iperm[r], iperm[c], v); the entries are then ordered by (new row, new
+    column) with a stable sort, so duplicates keep their stored order.
+    Returns (rowptr int64[n+1], col int32[nnz], val float64[nnz])."""
     n = A.n
     iperm = np.empty(n, dtype=np.int64)
     iperm[np.asarray(perm, dtype=np.int64)] = np.arange(n)
+    old_rowptr = np.asarray(A.rowptr, dtype=np.int64)
+    new_row = iperm[np.repeat(np.arange(n, dtype=np.int64), np.diff(old_rowptr))]
+    new_col = iperm[np.asarray(A.col, dtype=np.int64)]
+    order = np.lexsort((new_col, new_row))  # stable: last key is the primary one
     rowptr = np.zeros(n + 1, dtype=np.int64)
-    cols, vals = [], []
-    for r in range(n):
-        o = int(perm[r])
-        a, b = int(A.rowptr[o]), int(A.rowptr[o + 1])
-        c = iperm[A.col[a:b].astype(np.int64)]
-        order = np.argsort(c, kind="stable")
-        cols.append(c[order])
-        vals.append(A.val[a:b][order])
-        rowptr[r + 1] = rowptr[r] + (b - a)
-    col = np.concatenate(cols).astype(np.int32) if n else np.zeros(0, np.int32)
-    val = np.concatenate(vals) if n else np.zeros(0)
-    return rowptr, col, val
+    np.cumsum(np.bincount(new_row, minlength=n), out=rowptr[1:])
+    return rowptr, new_col[order].astype(np.int32), np.asarray(A.val, dtype=np.float64)[order]
 
 
 # ----------------------------------------------------------------------------

@@ -90,6 +90,8 @@ SIGNATURES = {
     "mpk_permute": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "mpk_run": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
     "mpk_run_baseline": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
+    "mpk_run_first": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
+    "mpk_run_baseline_first": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(mpk_recurrence), _P]),
     "mpk_run_sync": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P]),
     "mpk_plan_status": (ctypes.c_int32, [_P, _P]),
     "mpk_plan_destroy": (None, [_P]),

@@ -58,8 +58,15 @@ class ChebPropagator:
     """Chebyshev propagator: ``step(X, acc)`` writes U(dt) X to acc (both
     device, N x k, plan order).  Complex coefficients need a plan with
     nrhs = 2 (re, im columns of one complex state); real coefficients act
-    on every column.  ``baseline`` selects p back-to-back SpMV launches per
-    block instead of the level-blocked MPK."""
+    on every column.  ``baseline`` selects back-to-back SpMV launches per
+    block instead of the level-blocked MPK.
+
+    The degree M is covered by floor(M/p) blocks of the plan's p powers and,
+    when p does not divide M, one block of the remaining M mod p powers on
+    the same plan (Sec. 5: powers beyond p_m run as a further, shorter MPK
+    call).  Every block after the first continues the three-term recurrence
+    from the last two vectors of the previous blocks, v_{b p} and
+    v_{b p - 1}; with p = 1 the older one is the previous block's input."""
 
     def __init__(self, plan: Plan, coeffs):
         c = np.asarray(coeffs)
@@ -69,25 +76,28 @@ class ChebPropagator:
         if plan.nrhs > 2:
             raise ValueError("the recurrence epilogue handles nrhs <= 2")
         M = len(c) - 1
-        if M < 1 or M % plan.p != 0:
-            raise ValueError("the degree must be a positive multiple of the plan's p")
+        if M < 1:
+            raise ValueError("the degree must be at least 1")
         self.plan, self.M, self.p, self.c = plan, M, plan.p, c
         p = self.p
         if self.complex:
-            coef = np.stack([c[1:].real, c[1:].imag], 1).reshape(M // p, 2 * p)
             self.c0 = np.array([c[0].real, c[0].imag])
         else:
-            coef = np.asarray(c[1:], dtype=np.float64).reshape(M // p, p)
             self.c0 = np.array([float(c[0])])
+        # blocks: (first power index k0 of the block, number of powers)
+        self.blocks = [(1 + b * p, p) for b in range(M // p)]
+        if M % p:
+            self.blocks.append((1 + (M // p) * p, M % p))
         self._rec = []
-        for b in range(M // p):
+        for b, (k0, n) in enumerate(self.blocks):
+            ck = c[k0:k0 + n]
+            coef = (np.stack([ck.real, ck.imag], 1).reshape(-1) if self.complex
+                    else np.asarray(ck, dtype=np.float64))
+            alpha = np.full(n, 2.0)
+            gamma = np.full(n, -1.0)
             if b == 0:
-                alpha = np.array([1.0] + [2.0] * (p - 1))
-                gamma = np.array([0.0] + [-1.0] * (p - 1))
-            else:
-                alpha = np.full(p, 2.0)
-                gamma = np.full(p, -1.0)
-            self._rec.append((alpha, gamma, coef[b].copy()))
+                alpha[0], gamma[0] = 1.0, 0.0  # v_1 = A v_0
+            self._rec.append((alpha, gamma, coef.copy()))
         self._Y = None
 
     @classmethod
@@ -102,15 +112,18 @@ class ChebPropagator:
         import torch
 
         p = self.p
-        if self._Y is None or self._Y.shape[1:] != X.shape:
-            self._Y = torch.empty((2, p) + tuple(X.shape), dtype=torch.float64, device=X.device)
+        if self._Y is None or self._Y.shape[2:] != X.shape:
+            # three power blocks in turn: the block being written never
+            # overlaps the two vectors it continues from
+            self._Y = torch.empty((3, p) + tuple(X.shape), dtype=torch.float64, device=X.device)
         run = self.plan.run_baseline if baseline else self.plan.run
         x_in, y_prev = X, None
-        for b, (alpha, gamma, coef) in enumerate(self._rec):
-            Yb = self._Y[b % 2]
+        for b, ((k0, n), (alpha, gamma, coef)) in enumerate(zip(self.blocks, self._rec)):
+            Yb = self._Y[b % 3]
             rec = Recurrence(alpha, None, gamma, coef, self.complex, y_prev, acc,
                              coef0=self.c0 if b == 0 else None)
-            run(x_in, Yb, rec, stream=stream)
-            # the next block starts from v_{(b+1)p} with v_{(b+1)p - 1} before it
-            x_in, y_prev = Yb[p - 1], Yb[p - 2]
+            run(x_in, Yb, rec, stream=stream, powers=n)
+            # the next block continues from v_{k0+n-1} and the vector before it
+            y_prev = Yb[n - 2] if n >= 2 else x_in
+            x_in = Yb[n - 1]
         return acc

@@ -227,6 +227,7 @@ struct MpkArgs {
     const int32_t *dep_ptr;
     const int32_t *dep_rng;
     int32_t dep_lists;
+    int32_t p_run;  // powers computed (<= the plan's p); tickets of higher powers are skipped
 };
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
@@ -342,6 +343,22 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     const uint32_t epoch = s_epoch;
     const int counter = stream * (kMaxStripes / nS) + s_sub;
     const int sub = s_sub;
+    // A run of fewer powers than the plan's skips the tickets of the higher
+    // powers: nothing waits for them.  Thread 0 moves past them with further
+    // counter increments.
+    auto next_ticket = [&](int t0, uint32_t &kk) -> int {
+        int tn = t0;
+        while (tn < len && ((a.work[base + tn] & 63) + 1) > a.p_run) {
+            kk = __hip_atomic_fetch_add(stripe_counter(a, counter), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tn = (int)min<int64_t>((int64_t)sub + (int64_t)kk * S, len);
+        }
+        return tn;
+    };
+    if (threadIdx.x == 0 && a.p_run < MPK_MAX_POWER) {
+        uint32_t kk = 0;
+        s_next[0] = next_ticket(s_next[0], kk);
+    }
+    __syncthreads();
     int t = s_next[0];
     for (int it = 1; t < len; ++it) {
         const int w = a.work[base + t];
@@ -385,7 +402,11 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         // every wavefront waits until its stores have completed (vmcnt = 0)
         // before the workgroup barrier, after which the flag is published.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        if (threadIdx.x == 0) s_next[it & 1] = (int)min<int64_t>((int64_t)sub + (int64_t)kn * S, len);
+        if (threadIdx.x == 0) {
+            int tn = (int)min<int64_t>((int64_t)sub + (int64_t)kn * S, len);
+            if (a.p_run < MPK_MAX_POWER) tn = next_ticket(tn, kn);
+            s_next[it & 1] = tn;
+        }
         __syncthreads();
         if (threadIdx.x == 0) st_agent(a.flags + (int64_t)(q - 1) * a.ntiles + tile, epoch);
         t = s_next[it & 1];
@@ -906,23 +927,46 @@ mpk_status mpk_permute(const mpk_plan *plan, const double *in, double *out, int3
     return MPK_OK;
 }
 
-static mpk_status check_run_args(mpk_plan *plan, const double *X, double *Y) {
+// [a, a + abytes) and [b, b + bbytes) share a byte (null pointers share none)
+static bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a && b && a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+// Arguments of a run of `powers` powers: the plan is uploaded, the vectors
+// are given, and no buffer the run writes (Y: powers x N x k, acc: N x k)
+// overlaps another buffer of the run.
+static mpk_status check_run_args(mpk_plan *plan, const double *X, double *Y, int32_t powers,
+                                 const mpk_recurrence *rec) {
     if (!plan) return fail(MPK_ERR_ARG, "null plan");
     if (!plan->uploaded) return fail(MPK_ERR_STATE, "plan not uploaded (call mpk_plan_upload)");
-    if (plan->hp.n > 0 && (!X || !Y)) return fail(MPK_ERR_ARG, "null vector");
-    const int64_t NK = plan->hp.n * plan->hp.opt.nrhs;
-    const double *y0 = Y, *y1 = Y + NK * plan->hp.p;
-    if (plan->hp.n > 0 && X + NK > y0 && X < y1) return fail(MPK_ERR_ARG, "Y overlaps X");
+    if (powers < 1 || powers > plan->hp.p) return fail(MPK_ERR_ARG, "powers must be in [1, plan p]");
+    if (plan->hp.n == 0) return MPK_OK;
+    if (!X || !Y) return fail(MPK_ERR_ARG, "null vector");
+    const uint64_t vb = (uint64_t)plan->hp.n * plan->hp.opt.nrhs * 8, yb = vb * (uint64_t)powers;
+    if (overlaps(X, vb, Y, yb)) return fail(MPK_ERR_ARG, "Y overlaps X");
+    if (rec) {
+        if (overlaps(rec->y_prev, vb, Y, yb)) return fail(MPK_ERR_ARG, "Y overlaps y_prev");
+        if (overlaps(rec->acc, vb, Y, yb)) return fail(MPK_ERR_ARG, "Y overlaps acc");
+        if (overlaps(rec->acc, vb, X, vb)) return fail(MPK_ERR_ARG, "acc overlaps X");
+        if (overlaps(rec->acc, vb, rec->y_prev, vb)) return fail(MPK_ERR_ARG, "acc overlaps y_prev");
+    }
     return MPK_OK;
 }
 
 mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec, void *stream) {
-    mpk_status st = check_run_args(plan, X, Y);
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    return mpk_run_first(plan, plan->hp.p, X, Y, rec, stream);
+}
+
+mpk_status mpk_run_first(mpk_plan *plan, int32_t powers, const double *X, double *Y, const mpk_recurrence *rec,
+                         void *stream) {
+    mpk_status st = check_run_args(plan, X, Y, powers, rec);
     if (st != MPK_OK) return st;
     HostPlan &h = plan->hp;
     if (h.n == 0) return MPK_OK;
     RecArgs ra;
-    if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
+    if ((st = fill_rec(rec, powers, h.opt.nrhs, ra)) != MPK_OK) return st;
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
     MpkArgs a;
@@ -953,6 +997,8 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
     a.flags = plan->d_flags;
     a.ctrl = plan->d_ctrl;
     a.watchdog = h.opt.watchdog_spins > 0 ? h.opt.watchdog_spins : (int64_t)1 << 24;
+    // MPK_MAX_POWER marks a full run (no ticket is skipped)
+    a.p_run = powers == h.p ? MPK_MAX_POWER : powers;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.accum_f64, h.opt.nrhs, rec != nullptr, [&](auto d) {
         return decltype(d)::mpk(plan->workgroups, s, a, ra);
@@ -963,19 +1009,25 @@ mpk_status mpk_run(mpk_plan *plan, const double *X, double *Y, const mpk_recurre
 
 mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mpk_recurrence *rec,
                             void *stream) {
-    mpk_status st = check_run_args(plan, X, Y);
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    return mpk_run_baseline_first(plan, plan->hp.p, X, Y, rec, stream);
+}
+
+mpk_status mpk_run_baseline_first(mpk_plan *plan, int32_t powers, const double *X, double *Y,
+                                  const mpk_recurrence *rec, void *stream) {
+    mpk_status st = check_run_args(plan, X, Y, powers, rec);
     if (st != MPK_OK) return st;
     HostPlan &h = plan->hp;
     if (h.n == 0) return MPK_OK;
     RecArgs ra;
-    if ((st = fill_rec(rec, h.p, h.opt.nrhs, ra)) != MPK_OK) return st;
+    if ((st = fill_rec(rec, powers, h.opt.nrhs, ra)) != MPK_OK) return st;
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
     const int K = h.opt.nrhs;
     const int blocks = (int)(h.chunk_row.size() - 1);
     const int64_t NK = h.n * K;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    for (int q = 1; q <= h.p; ++q) {
+    for (int q = 1; q <= powers; ++q) {
         const double *x = q == 1 ? X : Y + (int64_t)(q - 2) * NK;
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
@@ -990,7 +1042,8 @@ mpk_status mpk_run_baseline(mpk_plan *plan, const double *X, double *Y, const mp
 }
 
 mpk_status mpk_run_sync(mpk_plan *plan, const double *X, double *Y, int32_t granularity, void *stream) {
-    mpk_status st = check_run_args(plan, X, Y);
+    if (!plan) return fail(MPK_ERR_ARG, "null plan");
+    mpk_status st = check_run_args(plan, X, Y, plan->hp.p, nullptr);
     if (st != MPK_OK) return st;
     if (granularity != MPK_SYNC_NODE && granularity != MPK_SYNC_WAVEFRONT)
         return fail(MPK_ERR_ARG, "granularity must be MPK_SYNC_NODE or MPK_SYNC_WAVEFRONT");

@@ -104,6 +104,9 @@ void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_
 int32_t chunk_nnz_host(int32_t k);
 // rows per chunk cap: bounds the chunk's row-pointer slice kept in LDS
 constexpr int32_t kChunkRows = 1024;
+// A ticket is the int32 tile * 64 + (power - 1) (powers <= 32 < 64), so a
+// plan holds fewer than 2^25 tiles.
+constexpr int64_t kMaxTiles = int64_t(1) << 25;
 
 // Breadth-first levels and root on the current GPU (plan_device.hip): the
 // same root, permutation and level pointers as the host planner, from the

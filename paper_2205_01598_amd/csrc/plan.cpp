@@ -499,6 +499,7 @@ mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &
     hp.group_tile.push_back((int32_t)hp.tile_group.size());
     hp.tile_row.push_back((int32_t)n);
     const int64_t T = (int64_t)hp.tile_group.size();
+    if (T >= kMaxTiles) return fail(MPK_ERR_UNSUPPORTED, "too many tiles (2^25 or more): raise tile_nnz");
 
     // dependency lists
     std::vector<int32_t> row_tile(n);
@@ -696,6 +697,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         hp.group_tile.push_back((int32_t)hp.tile_group.size());
         hp.tile_row.push_back((int32_t)n);
         const int64_t T = (int64_t)hp.tile_group.size();
+        if (T >= kMaxTiles) return fail(MPK_ERR_UNSUPPORTED, "too many tiles (2^25 or more): raise tile_nnz");
 
         // Point-to-point dependencies of each tile (Sec. 4.3).  By Eq. (4) a
         // tile of group g only reads rows of groups g-1, g and g+1.  For each

@@ -30,6 +30,42 @@ def _ptr(t):
     return ctypes.c_void_p(int(t.data_ptr()))
 
 
+def _check_vec(t, name: str, numel: int, at_least: bool = False, device: bool = True):
+    """A device buffer the kernels read or write: a contiguous float64 GPU
+    tensor of ``numel`` elements (or more with ``at_least``).  Raises
+    ValueError before anything reaches the library."""
+    if t is None:
+        raise ValueError(f"{name}: a tensor is required")
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_cuda"):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if str(t.dtype) != "torch.float64":
+        raise ValueError(f"{name}: dtype must be torch.float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    n = t.numel()
+    if (n < numel) if at_least else (n != numel):
+        want = f"at least {numel}" if at_least else f"{numel}"
+        raise ValueError(f"{name}: expected {want} elements, got {n}")
+    if device and not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU (cuda) tensor")
+
+
+def _check_rec(rec, powers: int, nk: int):
+    """Host coefficient arrays hold an entry per power (two for complex
+    coef and coef0); y_prev and acc are N x k device buffers."""
+    for nm in ("alpha", "beta", "gamma"):
+        if len(getattr(rec, nm)) < powers:
+            raise ValueError(f"recurrence {nm}: needs {powers} entries, got {len(getattr(rec, nm))}")
+    w = 2 if rec.complex_pairs else 1
+    if rec.coef is not None and len(rec.coef) < w * powers:
+        raise ValueError(f"recurrence coef: needs {w * powers} entries, got {len(rec.coef)}")
+    if rec.coef0 is not None and len(rec.coef0) < w:
+        raise ValueError(f"recurrence coef0: needs {w} entries, got {len(rec.coef0)}")
+    for nm in ("y_prev", "acc"):
+        if getattr(rec, nm) is not None:
+            _check_vec(getattr(rec, nm), nm, nk, device=False)
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -162,17 +198,40 @@ class Plan:
     # -- device calls ------------------------------------------------------------
     def permute(self, x, out, to_plan: bool, stream=None):
         k = 1 if x.dim() == 1 else x.shape[-1]
+        _check_vec(x, "in", self.n * k)
+        _check_vec(out, "out", self.n * k)
         check(lib().mpk_permute(self._h, _ptr(x), _ptr(out), int(k), int(to_plan), _stream(stream)))
         return out
 
-    def run(self, X, Y, rec: Recurrence | None = None, stream=None):
-        r = ctypes.byref(rec.struct()) if rec is not None else None
-        check(lib().mpk_run(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+    def _run_args(self, X, Y, rec, powers):
+        powers = self.p if powers is None else int(powers)
+        if not 1 <= powers <= self.p:
+            raise ValueError(f"powers must be in [1, {self.p}], got {powers}")
+        nk = self.n * self.nrhs
+        if rec is not None:
+            _check_rec(rec, powers, nk)
+        _check_vec(X, "X", nk, device=False)
+        _check_vec(Y, "Y", powers * nk, at_least=True, device=False)
+        for nm, t in (("X", X), ("Y", Y)) + ((("y_prev", rec.y_prev), ("acc", rec.acc)) if rec else ()):
+            if t is not None and not t.is_cuda:
+                raise ValueError(f"{nm}: must be a GPU (cuda) tensor")
+        return powers, (ctypes.byref(rec.struct()) if rec is not None else None)
+
+    def run(self, X, Y, rec: Recurrence | None = None, stream=None, powers: int | None = None):
+        """y_1..y_powers (default: all p) of X into Y (plan order)."""
+        powers, r = self._run_args(X, Y, rec, powers)
+        if powers == self.p:
+            check(lib().mpk_run(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+        else:
+            check(lib().mpk_run_first(self._h, powers, _ptr(X), _ptr(Y), r, _stream(stream)))
         return Y
 
-    def run_baseline(self, X, Y, rec: Recurrence | None = None, stream=None):
-        r = ctypes.byref(rec.struct()) if rec is not None else None
-        check(lib().mpk_run_baseline(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+    def run_baseline(self, X, Y, rec: Recurrence | None = None, stream=None, powers: int | None = None):
+        powers, r = self._run_args(X, Y, rec, powers)
+        if powers == self.p:
+            check(lib().mpk_run_baseline(self._h, _ptr(X), _ptr(Y), r, _stream(stream)))
+        else:
+            check(lib().mpk_run_baseline_first(self._h, powers, _ptr(X), _ptr(Y), r, _stream(stream)))
         return Y
 
     def run_sync(self, X, Y, granularity: str = "wavefront", stream=None):
@@ -180,6 +239,7 @@ class Plan:
         wavefront of independent nodes ("wavefront") instead of
         point-to-point flags."""
         g = {"node": 0, "wavefront": 1}[granularity]
+        self._run_args(X, Y, None, None)
         check(lib().mpk_run_sync(self._h, _ptr(X), _ptr(Y), g, _stream(stream)))
         return Y
 
@@ -206,10 +266,14 @@ class Spmv:
             self._h = None
 
     def run(self, x, y, stream=None):
+        _check_vec(x, "x", self.n * self.nrhs)
+        _check_vec(y, "y", self.n * self.nrhs)
         check(lib().spmv_run(self._h, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
     def powers(self, p: int, X, Y, stream=None):
+        _check_vec(X, "X", self.n * self.nrhs)
+        _check_vec(Y, "Y", int(p) * self.n * self.nrhs, at_least=True)
         check(lib().spmv_powers_run(self._h, int(p), _ptr(X), _ptr(Y), _stream(stream)))
         return Y
 

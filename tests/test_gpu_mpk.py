@@ -540,3 +540,66 @@ def test_line_closed_runs_without_fence(case):
             pl.run(X, Y1)
             pl.status()
             assert torch.equal(Y1, Y2)
+
+
+@pytest.mark.parametrize("p,M", [(1, 8), (2, 9), (3, 32), (8, 30)])
+@pytest.mark.parametrize("kind", ["heat", "schroedinger"])
+def test_chebyshev_p1_and_remainder_block(p, M, kind):
+    # Sec. 5 / Sec. 7: degree M as floor(M/p) blocks of p and one block of
+    # M mod p powers on the same plan (mpk_run_first); p = 1 carries the older
+    # recurrence vector from the previous block's input
+    from paper_2205_01598_amd.cheb import ChebPropagator
+
+    dev = _dev()
+    if kind == "heat":
+        A, _ = W.heat_operator_3d(10, 2)
+        x = W.uniform_vector(A.n, seed=5)
+        c = O.heat_coefficients(M, 4.0)
+        ref = O.cheb_propagate_real(A, x, c)
+        pl = Plan(A, p, 1 << 18, root_mode=1, tile_nnz=500, skew=2)
+    else:
+        A = W.anderson_3d(10, seed=5)
+        x = W.random_phase_state(A.n, seed=5)
+        c = O.cheb_coefficients(M, 6.0)
+        ref = O.cheb_propagate(A, x, c)
+        pl = Plan(A, p, 1 << 18, root_mode=1, nrhs=2, tile_nnz=500, skew=2)
+    perm = pl.arrays()[0].astype(np.int64)
+    prop = ChebPropagator(pl, c)
+    assert [n for _, n in prop.blocks] == [p] * (M // p) + ([M % p] if M % p else [])
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+    for baseline in (False, True):
+        acc = torch.full_like(X, float("nan"))
+        prop.step(X, acc, baseline=baseline)
+        pl.status()
+        h = np.empty(x.shape)
+        h[perm] = acc.cpu().numpy()
+        assert _rel_err(h, ref) <= 1e-12, f"baseline={baseline}"
+
+
+def test_run_rejects_overlapping_buffers():
+    # mpk_run: Y must not overlap X, y_prev or acc; acc must not overlap X or
+    # y_prev (the kernels read them while other tiles write)
+    dev = _dev()
+    A = W.stencil_2d(16, 5)
+    pl = Plan(A, 3, 1 << 16, nrhs=1)
+    n = A.n
+    buf = torch.zeros(8 * n, dtype=torch.float64, device=dev)
+    X, Y = buf[:n], buf[n:4 * n]
+    pl.run(X, Y)  # disjoint: fine
+    pl.status()
+    with pytest.raises(MpkError, match="Y overlaps X"):
+        pl.run(buf[:n], buf[n // 2:n // 2 + 3 * n])
+    rec = lambda **kw: Recurrence(np.ones(3), gamma=np.array([1.0, 0, 0]), coef=np.ones(3), **kw)  # noqa: E731
+    with pytest.raises(MpkError, match="Y overlaps y_prev"):
+        pl.run(X, Y, rec(y_prev=buf[2 * n:3 * n], acc=buf[5 * n:6 * n]))
+    with pytest.raises(MpkError, match="Y overlaps acc"):
+        pl.run(X, Y, rec(y_prev=buf[4 * n:5 * n], acc=buf[3 * n:4 * n]))
+    with pytest.raises(MpkError, match="acc overlaps X"):
+        pl.run(X, Y, rec(y_prev=buf[4 * n:5 * n], acc=buf[:n]))
+    with pytest.raises(MpkError, match="acc overlaps y_prev"):
+        pl.run(X, Y, rec(y_prev=buf[4 * n:5 * n], acc=buf[4 * n:5 * n]))
+    with pytest.raises(MpkError, match="Y overlaps y_prev"):
+        pl.run_baseline(X, Y, rec(y_prev=buf[3 * n:4 * n], acc=buf[5 * n:6 * n]))
+    # a valid recurrence run on the same buffers
+    pl.run(X, Y, rec(y_prev=buf[4 * n:5 * n], acc=buf[5 * n:6 * n]))
+    pl.status()

@@ -348,6 +348,144 @@ def test_lowp_rounding_rules():
     assert yf.tolist() == [float(np.float32(1 + 2.0 ** -8)), float(np.float32(1 + 3 * 2.0 ** -8)), 1.0]
 
 
+# Exact IEEE cases that fix the three steps of the mixed-precision product
+# (Sec. 3 extended by storage precision; readings in the oracle's header):
+#   (a) an FP32 running sum: 1 followed by eight 2^-24 terms stays exactly 1
+#       (each 1 + 2^-24 is a tie that rounds to even); an FP64 sum would give
+#       1 + 2^-21;
+#   (b) the input vector rounded to FP32 before the product: 3 * x with
+#       x = 1 + 2^-24 rounds x to 1 and gives exactly 3; without that rounding
+#       the FP32 product 3 + 3*2^-24 rounds to 3 + 2^-22;
+#   (c) products rounded before the add, no fused multiply-add: -1 + a*x with
+#       a = x = 1 + 2^-12 (FP32 storage) gives 2^-11, since the product
+#       1 + 2^-11 + 2^-24 is a tie rounded to 1 + 2^-11, where a fused
+#       multiply-add gives 2^-11 + 2^-24; with BF16 storage (8 significant
+#       bits) a = 1 + 2^-7, x = 1 + 2^-17: 2^-7 + 2^-17 against
+#       2^-7 + 2^-17 + 2^-24.
+def _lowp_pin_cases():
+    t = 2.0 ** -24
+    both = ("f32", "bf16")
+    cases = []
+    A = W.CSR(1, np.array([0, 9], np.int64), np.zeros(9, np.int32), np.array([1.0] + [t] * 8))
+    cases.append((A, np.ones(1), 1.0, both))
+    A = W.CSR(1, np.array([0, 1], np.int64), np.zeros(1, np.int32), np.array([3.0]))
+    cases.append((A, np.array([1.0 + t]), 3.0, both))
+    for a, xv, want, dts in ((1.0 + 2.0 ** -12, 1.0 + 2.0 ** -12, 2.0 ** -11, ("f32",)),
+                             (1.0 + 2.0 ** -7, 1.0 + 2.0 ** -17, 2.0 ** -7 + 2.0 ** -17, both)):
+        A = W.CSR(2, np.array([0, 2, 2], np.int64), np.array([1, 0], np.int32), np.array([-1.0, a]))
+        cases.append((A, np.array([xv, 1.0]), want, dts))
+    return cases
+
+
+def _lowp_pins_hold(fn):
+    """True iff ``fn(A, x, p, dtype)`` reproduces every pin exactly in the
+    storage precisions it names."""
+    for A, x, want, dts in _lowp_pin_cases():
+        for dt in dts:
+            if fn(A, x, 1, dt)[0][0] != want:
+                return False
+    return True
+
+
+def test_lowp_ieee_pins():
+    assert _lowp_pins_hold(O.spmv_powers_lowp)
+
+
+def _lowp_mutant(sum64=False, round_x=True, fused=False):
+    # plausible mistakes in a copy of the product definition (CPU only)
+    def fn(A, x, p, dt):
+        a = O.round_values(A, dt).val.astype(np.float32)
+        y, v = [], np.asarray(x, np.float64)
+        for _ in range(p):
+            xin = v.astype(np.float32) if round_x else v
+            out = np.empty(A.n)
+            for r in range(A.n):
+                s = np.float64(0) if sum64 else np.float32(0)
+                for j in range(A.rowptr[r], A.rowptr[r + 1]):
+                    if fused:
+                        s = np.float32(np.float64(a[j]) * np.float64(xin[A.col[j]]) + np.float64(s))
+                    elif sum64:
+                        s = s + np.float64(np.float32(a[j] * xin[A.col[j]]))
+                    else:
+                        s = np.float32(s + np.float32(np.float64(a[j]) * np.float64(xin[A.col[j]])))
+                out[r] = float(s)
+            y.append(out)
+            v = out
+        return np.array(y)
+    return fn
+
+
+def test_lowp_pins_reject_planted_mistakes():
+    # the faithful copy passes; each planted mistake fails at least one pin
+    assert _lowp_pins_hold(_lowp_mutant())
+    assert not _lowp_pins_hold(_lowp_mutant(sum64=True))
+    assert not _lowp_pins_hold(_lowp_mutant(round_x=False))
+    assert not _lowp_pins_hold(_lowp_mutant(fused=True))
+
+
+def test_threaded_oracle_is_bit_identical():
+    # Sec. 6 baseline: rows shared among threads, each row summed in stored order
+    rng = np.random.default_rng(11)
+    A = W.random_small_csr(3000, 6.0 / 3000, rng, symmetric_pattern=False, empty_rows=0.05, duplicates=0.05)
+    for k in (1, 3):
+        x = rng.uniform(-1, 1, (A.n, k)) if k > 1 else rng.uniform(-1, 1, A.n)
+        ref = O.spmv_powers(A, x, 5)
+        for t in (2, 3, 8):
+            assert np.array_equal(O.spmv_powers(A, x, 5, threads=t), ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_permute_symmetric_brute_force(seed):
+    # (P A P^T)[i, j] = A[perm[i], perm[j]] on dense copies (duplicates summed),
+    # columns ascending per row, duplicates in their stored order
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(1, 40))
+    A = W.random_small_csr(n, float(rng.uniform(0.05, 0.4)), rng, symmetric_pattern=bool(seed % 2),
+                           empty_rows=0.1, duplicates=0.2)
+    perm = rng.permutation(n).astype(np.int32)
+    rp, col, val = O.permute_symmetric(A, perm)
+    B = np.zeros((n, n))
+    for r in range(n):
+        assert np.all(np.diff(col[rp[r]:rp[r + 1]]) >= 0)
+        for j in range(rp[r], rp[r + 1]):
+            B[r, col[j]] += val[j]
+    D = A.to_dense()
+    assert np.array_equal(B, D[np.ix_(perm, perm)])
+    assert np.array_equal(np.diff(rp), np.diff(A.rowptr)[perm])
+    # duplicate order: row 0 holds (1, 5.0), (0, 1.0), (1, 7.0); perm swaps 0 and 1
+    E = W.CSR(2, np.array([0, 3, 3], np.int64), np.array([1, 0, 1], np.int32), np.array([5.0, 1.0, 7.0]))
+    rp, col, val = O.permute_symmetric(E, np.array([1, 0], np.int32))
+    assert rp.tolist() == [0, 0, 3] and col.tolist() == [0, 0, 1] and val.tolist() == [5.0, 7.0, 1.0]
+
+
+def test_level_nnz_brute_force():
+    # N_nz of every level (Eq. 5) counted entry by entry, and the closed form
+    # of the path graph 0-1-...-(n-1) with diagonal from vertex 0: one vertex
+    # per level, 2 stored entries at the ends and 3 inside
+    rng = np.random.default_rng(21)
+    A = W.random_small_csr(500, 0.01, rng, symmetric_pattern=True, empty_rows=0.1, duplicates=0.1)
+    perm, lp = O.bfs_levels(A, 0)
+    lvl = np.empty(A.n, np.int64)
+    for i in range(len(lp) - 1):
+        lvl[perm[lp[i]:lp[i + 1]]] = i
+    count = np.zeros(len(lp) - 1, np.int64)
+    for r in range(A.n):
+        for _ in range(A.rowptr[r], A.rowptr[r + 1]):
+            count[lvl[r]] += 1
+    assert np.array_equal(O.level_nnz(A, perm, lp), count)
+    n = 7
+    rows, cols = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+    P = W.CSR(n, np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64),
+              np.array(cols, np.int32), np.ones(len(cols)))
+    perm, lp = O.bfs_levels(P, 0)
+    assert O.level_nnz(P, perm, lp).tolist() == [2, 3, 3, 3, 3, 3, 2]
+
+
 def test_round_values_nearest_even():
     # the worked ties of the rounding rules, then brute force: the BF16 value
     # is the nearer of the two BF16 neighbours of the FP32 value (ties to an
