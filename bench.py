@@ -127,8 +127,22 @@ def rel_errs(Y, ref):
     return [float(np.linalg.norm(Y[q] - ref[q]) / np.linalg.norm(ref[q])) for q in range(ref.shape[0])]
 
 
+def oracle_threads():
+    """Host threads for the oracle's row-parallel variant: every core this
+    process may run on, capped by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(cap))) if cap.isdigit() and int(cap) > 0 else n
+
+
+def fmt(v):
+    return float(f"{v:.3e}")
+
+
 def bench_small_2d(torch, Plan, W, dev):
     """64 x 64 5-point Laplacian, p = 4 (cache- and launch-latency-bound)."""
+    import oracle as O
+
     A = W.stencil_2d(64, 5)
     x = W.uniform_vector(A.n, seed=0)
     pl = Plan(A, 4, 64 * 1024, root_mode=1, tile_nnz=2048)
@@ -136,21 +150,29 @@ def bench_small_2d(torch, Plan, W, dev):
     X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
     Y = torch.empty((4, A.n), dtype=torch.float64, device=dev)
     tb = timed(torch, lambda: pl.run_baseline(X, Y), 200, 20)
+    Yb = Y.clone()
     tm = timed(torch, lambda: pl.run(X, Y), 200, 20)
     pl.status()
+    Yo = np.empty((4, A.n))
+    Yo[:, perm] = Y.cpu().numpy()
+    parity = {"max_rel_err_vs_oracle": fmt(max(rel_errs(Yo, O.spmv_powers(A, x, 4)))),
+              "bit_equal_to_baseline": bool(torch.equal(Y, Yb))}
     G = pl.info()["n_groups"]
     ladder = {"level_groups": G,
               "launch_per_node_us": round(timed(torch, lambda: pl.run_sync(X, Y, "node"), 100, 10) * 1e3, 2),
               "launch_per_wavefront_us": round(timed(torch, lambda: pl.run_sync(X, Y, "wavefront"), 100, 10) * 1e3, 2),
               "p2p_flags_us": round(tm * 1e3, 2)}
     return {"workload": "5-point Laplacian 64^2, p=4", "mpk_us": round(tm * 1e3, 2),
-            "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3), "sync_ladder": ladder}
+            "baseline_us": round(tb * 1e3, 2), "speedup": round(tb / tm, 3), "sync_ladder": ladder,
+            "parity": parity}
 
 
 def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
     """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8.
-    Low-precision errors are measured against the FP64 run of the same
-    steps (whose agreement with the oracle the tests establish)."""
+    Every configuration the autotuner picks is checked in the same run: one
+    step of the MPK equals the baseline's bit for bit, and ten steps are
+    compared with ten steps of the FP64 oracle (relative error per step)."""
+    import oracle as O
     from paper_2205_01598_amd import tune
     from paper_2205_01598_amd.cheb import ChebPropagator
 
@@ -158,7 +180,13 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
     x = W.random_phase_state(A.n, seed=0)
     M, p, r_dt = 32, 8, 10.0
     out = {"workload": "Anderson 128^3 (W=16, open BC, A=H/14), degree 32, p=8, r*dt=10, complex state"}
-    ref = None
+    t0 = time.time()
+    coeffs = O.cheb_coefficients(M, r_dt)
+    ref, state = [], x
+    for _ in range(steps_err):
+        state = O.cheb_propagate(A, state, coeffs, threads=oracle_threads())
+        ref.append(state)
+    log(f"chebyshev oracle: {steps_err} steps in {time.time() - t0:.1f}s")
     for dt in ("f64", "f32", "bf16"):
         pl = Plan(A, p, 256 << 20, root_mode=1, nrhs=2, val_dtype=dt, skew=2, tile_nnz=8192)
         perm = pl.arrays()[0].astype(np.int64)
@@ -166,6 +194,7 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
         X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
         acc = torch.empty_like(X)
         tb = timed(torch, lambda: prop.step(X, acc, baseline=True), 20, 3)
+        acc_base = acc.clone()
         # the autotuner over a few (C, tile, skew); the matrix fits the
         # Infinity Cache, so smaller budgets than the headline's are tried
         cands = [dict(cache_mb=C, tile_nnz=t, skew=s) for C, t, s in
@@ -175,7 +204,7 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
         pl.status()
         ent = {"step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4), "speedup": round(tb / tm, 3),
                "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1),
-               "config": cfg}
+               "config": cfg, "bit_equal_to_baseline": bool(torch.equal(acc, acc_base))}
         if dt == "f64":
             # the working set fits the 256 MB Infinity Cache: also time each
             # step after reading 512 MB of other data
@@ -195,11 +224,8 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
             h[perm] = nxt.cpu().numpy()
             states.append(h)
             state = nxt
-        if dt == "f64":
-            ref = states
-        else:
-            ent["rel_err_vs_fp64_per_step"] = [float(f"{np.linalg.norm(a - b) / np.linalg.norm(b):.3e}")
-                                               for a, b in zip(states, ref)]
+        ent["rel_err_vs_oracle_per_step"] = [fmt(np.linalg.norm(a - b) / np.linalg.norm(b))
+                                             for a, b in zip(states, ref)]
         ent["norm_after_steps"] = float(f"{np.linalg.norm(states[-1]):.12f}")
         out[dt] = ent
         del pl, prop
@@ -210,6 +236,7 @@ def bench_heat(torch, Plan, W, dev):
     """Heat equation on 160^3 with finite differences of order 2, 4, 6
     (Table 3), degree-32 Chebyshev step (tau = 70, coefficients below 1e-4
     from degree 32 on) as 4 MPK blocks of p = 8, real coefficients."""
+    import oracle as O
     from paper_2205_01598_amd.cheb import ChebPropagator, degree_for_cutoff
 
     M, p, tau = 32, 8, 70.0
@@ -228,9 +255,14 @@ def bench_heat(torch, Plan, W, dev):
         tb = timed(torch, lambda: prop.step(X, accb, baseline=True), 10, 2)
         pl.status()
         diff = float((acc - accb).norm() / accb.norm())
+        ref = O.cheb_propagate_real(A, x, O.heat_coefficients(M, tau), threads=oracle_threads())
+        h = np.empty(A.n)
+        h[perm] = acc.cpu().numpy()
         out[f"order{order}"] = {"nnz": A.nnz, "step_ms": round(tm, 4), "baseline_step_ms": round(tb, 4),
                                 "speedup": round(tb / tm, 3), "gflops": round(2.0 * A.nnz * M / tm / 1e6, 1),
                                 "mpk_vs_baseline_rel_diff": float(f"{diff:.3e}"),
+                                "bit_equal_to_baseline": bool(torch.equal(acc, accb)),
+                                "rel_err_vs_oracle": fmt(np.linalg.norm(h - ref) / np.linalg.norm(ref)),
                                 "norm_ratio": float(f"{float(acc.norm()) / float(X.norm()):.6e}")}
         del pl, prop, A
     return out
@@ -239,6 +271,7 @@ def bench_heat(torch, Plan, W, dev):
 def bench_multi_rhs(torch, Plan, W, dev):
     """Random geometric graph, N = 2M, ~16 nnz/row, p = 6, k = 4..32, tile
     and group shapes picked by the autotuner."""
+    import oracle as O
     from paper_2205_01598_amd import tune
 
     A, _ = W.random_geometric(2_000_000, 16.0, seed=0)
@@ -251,12 +284,20 @@ def bench_multi_rhs(torch, Plan, W, dev):
         Y = torch.empty((6, A.n, k), dtype=torch.float64, device=dev)
         pl.retune(6, 256 << 20, root_mode=1, nrhs=k)
         tb = timed(torch, lambda: pl.run_baseline(X, Y), 5, 2)
+        Yb = Y.clone()
         cands = [dict(cache_mb=C, skew=s, tile_nnz=t) for C, s, t in
                  ((256, 2, 8192), (128, 2, 2048), (128, 3, 4096), (64, 3, 2048))]
         cfg, tm, _ = tune.autotune(torch, pl, 6, cands, lambda: pl.run(X, Y), nrhs=k)
+        pl.run(X, Y)
+        pl.status()
+        ref = O.spmv_powers(A, Xh, 6, threads=oracle_threads())
+        Yo = np.empty((6, A.n, k))
+        Yo[:, perm] = Y.cpu().numpy()
         out[f"k{k}"] = {"mpk_ms": round(tm, 4), "baseline_ms": round(tb, 4), "speedup": round(tb / tm, 3),
-                        "gflops": round(2.0 * A.nnz * 6 * k / tm / 1e6, 1), "config": cfg}
-        del X, Y
+                        "gflops": round(2.0 * A.nnz * 6 * k / tm / 1e6, 1), "config": cfg,
+                        "max_rel_err_vs_oracle": fmt(max(rel_errs(Yo, ref))),
+                        "bit_equal_to_baseline": bool(torch.equal(Y, Yb))}
+        del X, Y, Yb, ref, Yo
     return out
 
 
@@ -282,7 +323,13 @@ def bench_thin_levels(torch, Plan, W, dev):
     pl.run(X, Y)
     pl.status()
     flop = 2.0 * A.nnz * p
+    import oracle as O
+
+    Yo = np.empty((p, A.n))
+    Yo[:, perm] = Y.cpu().numpy()
+    err = fmt(max(rel_errs(Yo, O.spmv_powers(A, x, p, threads=oracle_threads()))))
     return {"workload": f"2D 9-point stencil 4096^2, n={A.n} nnz={A.nnz}, p={p}", "levels": pl.info()["n_levels"],
+            "max_rel_err_vs_oracle": err,
             "level_groups": pl.info()["n_groups"], "mpk_ms": round(tm, 4), "baseline_ms": round(tb, 4),
             "speedup": round(tb / tm, 3), "gflops": round(flop / tm / 1e6, 1), "config": cfg,
             "bit_equal_to_baseline": bool(torch.equal(Y, ref)), "runs_ms": runs}
@@ -386,19 +433,35 @@ def bench_learned_tuner(torch, plan, X, Y, p, log):
 
 
 def cpu_baseline_leg(A, x, p, flop):
-    """The CPU oracle (plain C, FP64, one host thread) timed on the same
-    input; its output also gives the FP64 error of the GPU result."""
+    """The CPU oracle (plain C, FP64) timed on the same input, the way the
+    paper runs its baseline (Sec. 6): the rows of every SpMV shared among all
+    host threads this process may use (OpenMP, static schedule), and on one
+    thread.  Both give the same result bit for bit; it is also the FP64
+    reference of the GPU result."""
     import oracle as O
 
-    runs = []
-    while sum(runs) < 10.0 and len(runs) < 8:
+    threads = oracle_threads()
+    runs, ref = [], None
+    while sum(runs) < 10.0 and len(runs) < 40:
         t0 = time.time()
-        ref = O.spmv_powers(A, x, p)
+        ref = O.spmv_powers(A, x, p, threads=threads)
         runs.append(time.time() - t0)
-    cpu_s = float(np.mean(runs))
-    cpu = {"value": round(flop / cpu_s / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-           "sample": f"{len(runs)} full FP64 p={p} runs (p back-to-back CSR SpMVs) of the same 160^3 matrix, "
-                     f"mean {cpu_s:.2f} s (min {min(runs):.2f} s) on one host thread of {cpu_model()}"}
+    one = []
+    while sum(one) < 10.0 and len(one) < 8:
+        t0 = time.time()
+        ref1 = O.spmv_powers(A, x, p)
+        one.append(time.time() - t0)
+    same = bool(np.array_equal(ref1, ref))
+    del ref1
+    cpu_s, one_s = float(np.mean(runs)), float(np.mean(one))
+    cpu = {"value": round(flop / cpu_s / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(runs)} full FP64 p={p} runs (p back-to-back CSR SpMVs, rows shared among {threads} "
+                     f"OpenMP threads, static schedule) of the same 160^3 matrix, mean {cpu_s:.3f} s "
+                     f"(min {min(runs):.3f} s), on {cpu_model()} ({len(os.sched_getaffinity(0))} cores in the "
+                     f"affinity mask)",
+           "single_thread": {"value": round(flop / one_s / 1e9, 3), "cores": 1,
+                             "sample": f"{len(one)} runs, mean {one_s:.2f} s (min {min(one):.2f} s)"},
+           "threaded_equals_single_thread_bitwise": same}
     return cpu, ref
 
 
@@ -520,6 +583,30 @@ def main():
               "p2p_flags_ms": round(ms, 4), "baseline_ms": round(t_base, 4)}
     log(f"sync ladder: {ladder}")
 
+    # ---- CPU oracle (FP64; all host threads and one) -----------------------------------
+    ref = None
+    cpu = None
+    headline_parity = {}
+    if not args.no_cpu:
+        import oracle as O
+
+        cpu, ref = cpu_baseline_leg(A, x, p, flop)
+        errs = rel_errs(Yh, ref)
+        log(f"cpu oracle {cpu['sample']}; MPK FP64 max rel err {max(errs):.2e}")
+        # bit for bit: the oracle on the plan's renumbered matrix and input sums
+        # every row in the kernel's order
+        t0 = time.time()
+        rp, pc, pv = O.permute_symmetric(A, perm)
+        B_plan = W.CSR(n, rp, pc, pv)
+        del rp, pc, pv
+        xp = np.ascontiguousarray(x[perm])
+        ref_plan = O.spmv_powers(B_plan, xp, p, threads=oracle_threads())
+        plan_order_y = Y.cpu().numpy()
+        headline_parity = {"max_rel_err_vs_oracle": fmt(max(errs)),
+                           "bit_equal_to_oracle_on_plan_matrix": bool(np.array_equal(plan_order_y, ref_plan))}
+        del ref_plan, plan_order_y
+        log(f"plan-order oracle check in {time.time() - t0:.1f}s: {headline_parity}")
+
     # ---- recursive level refinement (Sec. 4.4) on the same matrix and launch options ----
     recursion = {"unrefined": {"ms": round(ms, 4), "level_groups": G, "violating_groups": info["violating_groups"]}}
     if not args.only_main:
@@ -540,6 +627,8 @@ def main():
                                       "max_stage": ri["max_stage"], "dep_ranges_per_tile":
                                       round(ri["n_dep_ranges"] / ri["n_tiles"], 2), "plan_seconds": round(ps, 2),
                                       "max_rel_diff_vs_unrefined": float(f"{max(rel_errs(Yr, Yh)):.3e}")}
+            if ref is not None:
+                recursion[f"s_m={sm}"]["max_rel_err_vs_oracle"] = fmt(max(rel_errs(Yr, ref)))
             del pr, Xr
         # bulky levels: the same matrix from an interior root (vertex 0 of the
         # random relabelling), and a power-law graph whose BFS levels are few
@@ -560,11 +649,14 @@ def main():
                 Yr = np.empty((pw, Aw.n))
                 Yr[:, wperm] = Yw.cpu().numpy()
                 if ref_w is None:
-                    ref_w = Yr
+                    import oracle as O
+
+                    ref_w = ref if (Aw is A and ref is not None) else O.spmv_powers(Aw, xw, pw,
+                                                                                    threads=oracle_threads())
                 wi = pw_plan.info()
                 ent[f"s_m={sm}"] = {"ms": round(tw, 4), "level_groups": wi["n_groups"],
                                     "violating_groups": wi["violating_groups"], "units": wi["n_units"],
-                                    "max_rel_diff_vs_s_m=0": float(f"{max(rel_errs(Yr, ref_w)):.3e}")}
+                                    "max_rel_err_vs_oracle": fmt(max(rel_errs(Yr, ref_w)))}
                 del pw_plan, Xw, Yw
             ent["workload"] = f"n={Aw.n} nnz={Aw.nnz} p={pw}"
             recursion[name] = ent
@@ -581,15 +673,13 @@ def main():
         cq, tq, _ = tune.autotune(torch, plan, q, cands, lambda: plan.run(X, Yq))
         other[f"p{q}"] = {"ms": round(tq, 4), "gflops": round(2.0 * nnz * q / tq / 1e6, 1),
                           "baseline_ms": round(tb, 4), "speedup": round(tb / tq, 3), "config": cq}
+        if ref is not None:
+            plan.run(X, Yq)
+            plan.status()
+            Yo = np.empty((q, n))
+            Yo[:, perm] = Yq.cpu().numpy()
+            other[f"p{q}"]["max_rel_err_vs_oracle"] = fmt(max(rel_errs(Yo, ref[:q])))
         del Yq
-
-    # ---- CPU oracle (FP64, single thread) ------------------------------------------
-    ref = None
-    cpu = None
-    if not args.no_cpu:
-        cpu, ref = cpu_baseline_leg(A, x, p, flop)
-        errs = rel_errs(Yh, ref)
-        log(f"cpu oracle {cpu['sample']}; MPK FP64 max rel err {max(errs):.2e}")
 
     # ---- mixed precision ------------------------------------------------------------
     mixed = {}
@@ -601,6 +691,7 @@ def main():
             pm = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, val_dtype=dt, accum_f64=acc, skew=cfg["skew"],
                       tile_nnz=cfg["tile_nnz"])
             tbm = timed(torch, lambda: pm.run_baseline(X, Y), 5, 2)
+            Ybase = Y.clone()
             # the same small sweep as for FP64 (smaller values shift the best tile)
             mc = tune.autotune(torch, pm, p, cands + ([] if args.quick else
                                                       [dict(cache_mb=256, skew=2, tile_nnz=12288),
@@ -611,11 +702,24 @@ def main():
             ent = {"ms": round(tm, 4), "gflops": round(flop / tm / 1e6, 1), "baseline_ms": round(tbm, 4),
                    "speedup": round(tbm / tm, 3), "speedup_vs_fp64_baseline": round(t_base / tm, 3),
                    "config": mc}
+            pm.run(X, Y)
+            pm.status()
+            ent["bit_equal_to_baseline"] = bool(torch.equal(Y, Ybase))
             Ym = np.empty((p, n))
             Ym[:, perm] = Y.cpu().numpy()
-            ent["rel_err_vs_fp64_per_power"] = [float(f"{e:.3e}") for e in rel_errs(Ym, Yh)]
+            if ref is not None:
+                # the stated error: against the FP64 oracle
+                ent["rel_err_vs_fp64_oracle_per_power"] = [fmt(e) for e in rel_errs(Ym, ref)]
+                # parity: the oracle's definition of this arithmetic on the
+                # plan's matrix, bit for bit
+                if acc:
+                    dref = O.spmv_powers(O.round_values(B_plan, dt), xp, p, threads=oracle_threads())
+                else:
+                    dref = O.spmv_powers_lowp(B_plan, xp, p, dt)
+                ent["bit_equal_to_oracle_definition"] = bool(np.array_equal(Y.cpu().numpy(), dref))
+                del dref
             mixed[dt + ("_acc64" if acc else "")] = ent
-            del pm
+            del pm, Ybase
 
     extra = {}
     if not args.no_extra:
@@ -674,6 +778,7 @@ def main():
     }
     if ref is not None:
         out["fp64_max_rel_err"] = float(f"{max(rel_errs(Yh, ref)):.3e}")
+        out["parity"] = headline_parity
     print(json.dumps(out), flush=True)
 
 

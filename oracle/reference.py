@@ -275,22 +275,23 @@ def cheb_coefficients(M: int, r_dt: float, c_dt: float = 0.0) -> np.ndarray:
     return c * np.exp(-1j * c_dt)
 
 
-def cheb_propagate(A, x, coeffs) -> np.ndarray:
+def cheb_propagate(A, x, coeffs, threads: int = 1) -> np.ndarray:
     """One time step x' = sum_k c_k v_k with v_0 = x, v_1 = A x,
     v_{k+1} = 2 A v_k - v_{k-1} (Eq. 7-8).
 
     ``x`` is complex, given as (n, 2) [re, im]; A is real, so each product is
-    an SpMV on the two real columns.  Returns (n, 2)."""
+    an SpMV on the two real columns.  Returns (n, 2).  ``threads`` is passed
+    to spmv_powers (same result)."""
     xc = np.asarray(x, dtype=np.float64)
     M = len(coeffs) - 1
     v_prev = xc.copy()
     acc = coeffs[0].real * v_prev + coeffs[0].imag * np.stack([-v_prev[:, 1], v_prev[:, 0]], 1)
     if M == 0:
         return acc
-    v = spmv_powers(A, v_prev, 1)[0]
+    v = spmv_powers(A, v_prev, 1, threads)[0]
     acc += coeffs[1].real * v + coeffs[1].imag * np.stack([-v[:, 1], v[:, 0]], 1)
     for k in range(2, M + 1):
-        av = spmv_powers(A, v, 1)[0]
+        av = spmv_powers(A, v, 1, threads)[0]
         v_next = 2.0 * av - v_prev
         acc += coeffs[k].real * v_next + coeffs[k].imag * np.stack([-v_next[:, 1], v_next[:, 0]], 1)
         v_prev, v = v, v_next
@@ -310,17 +311,17 @@ def heat_coefficients(M: int, tau: float) -> np.ndarray:
     return (2.0 - (k == 0)) * ((-1.0) ** k) * iv(k, tau) * np.exp(-tau)
 
 
-def cheb_propagate_real(A, x, coeffs) -> np.ndarray:
+def cheb_propagate_real(A, x, coeffs, threads: int = 1) -> np.ndarray:
     """One time step x' = sum_k c_k v_k with real coefficients and a real
     state (n,): v_0 = x, v_1 = A x, v_{k+1} = 2 A v_k - v_{k-1} (Eq. 7-8)."""
     v_prev = np.asarray(x, dtype=np.float64).copy()
     acc = coeffs[0] * v_prev
     if len(coeffs) == 1:
         return acc
-    v = spmv_powers(A, v_prev, 1)[0]
+    v = spmv_powers(A, v_prev, 1, threads)[0]
     acc = acc + coeffs[1] * v
     for k in range(2, len(coeffs)):
-        v_next = 2.0 * spmv_powers(A, v, 1)[0] - v_prev
+        v_next = 2.0 * spmv_powers(A, v, 1, threads)[0] - v_prev
         acc = acc + coeffs[k] * v_next
         v_prev, v = v, v_next
     return acc
