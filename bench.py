@@ -355,11 +355,11 @@ def probe():
         ids = torch.full((wg,), -1, dtype=torch.int32, device=dev)
         xcd_ids(ids, wg, spin)
         h = ids.cpu().numpy()
-        exp = np.arange(wg) % 8
-        place[f"wg{wg}_spin{spin}"] = {"mismatch": int((h != exp).sum()),
+        exp = (h[0] + np.arange(wg)) % 8
+        place[f"wg{wg}_spin{spin}"] = {"first_xcd": int(h[0]), "mismatch": int((h != exp).sum()),
                                        "per_xcd": np.bincount(h[h >= 0], minlength=8).tolist()}
     report["xcd_placement"] = place
-    print(f"XCD placement (mismatches against b % 8): {place}", flush=True)
+    print(f"XCD placement (mismatches against (ids[0] + b) % 8): {place}", flush=True)
     # ---- flag hop latency ---------------------------------------------------------------
     flags = torch.zeros(64, dtype=torch.int32, device=dev)
     out = torch.zeros(2, dtype=torch.int64, device=dev)

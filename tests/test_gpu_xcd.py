@@ -1,9 +1,12 @@
 """GPU: XCD placement and flag-hop probes (include/mpk.h, mpk_xcd_ids and
 mpk_hop_probe).
 
-The XCD-sliced ticket streams (mpk_options.xcd_streams = 8) assume that
-workgroup b of a launch runs on XCD b % 8; this checks it on the hardware
-register for the grid shapes the persistent kernel launches.  The hop probe
+The XCD-sliced ticket streams (mpk_options.xcd_streams = 8) assume that the
+workgroups b, b + 8, b + 16, ... of a launch share one XCD.  The dispatcher
+deals workgroups to the 8 XCDs round-robin, starting where its previous
+launch stopped, so workgroup b runs on XCD (b + r) % 8 with r fixed for the
+launch (r = 0 in a fresh process); this checks that on the hardware register
+for the grid shapes the persistent kernel launches.  The hop probe
 must complete at agent scope, the scope every dependency flag uses.
 """
 import numpy as np
@@ -22,13 +25,13 @@ def _dev():
 
 
 @pytest.mark.parametrize("wg,spin", [(8, 0), (1024, 0), (2048, 100), (4096, 0)])
-def test_workgroup_xcd_is_block_index_mod_8(wg, spin):
+def test_workgroups_round_robin_over_xcds(wg, spin):
     dev = _dev()
     ids = torch.full((wg,), -1, dtype=torch.int32, device=dev)
     xcd_ids(ids, wg, spin)
     h = ids.cpu().numpy()
     assert (h >= 0).all() and (h < 8).all()
-    np.testing.assert_array_equal(h, np.arange(wg) % 8)
+    np.testing.assert_array_equal(h, (h[0] + np.arange(wg)) % 8)
 
 
 @pytest.mark.parametrize("peer", [1, 8])
