@@ -93,8 +93,9 @@ typedef struct mpk_options {
                                  reuse window of s*p + 1 groups instead of p + 1) */
     int32_t xcd_streams;      /* 1 (default): one ticket sequence for the whole grid.  8: the tiles
                                  of every level group are cut into 8 slices and slice s is run by
-                                 workgroups with blockIdx % 8 == s (the XCD they are dispatched to
-                                 on MI355X), so a tile meets the same L2 at every power */
+                                 the workgroups with blockIdx % 8 == s, which share one XCD on
+                                 MI355X (the dispatcher deals workgroups round-robin over the 8
+                                 XCDs), so a tile meets the same L2 at every power */
     int32_t plan_on_device;   /* 1: mpk_plan_create uses the current GPU: graph, levels (root search,
                                  breadth-first levels) and the renumbered matrix for a pattern with
                                  sorted symmetric rows; for other patterns the host builds the graph
@@ -364,7 +365,7 @@ mpk_status mpk_bw_probe(const void *buf, uint64_t bytes, int32_t reps, int32_t w
 /* The same probe with `loads_per_thread` (1, 2, 4 or 8) independent 16-byte
  * loads per thread in flight and the buffer cut into `parts` (1 or 8) equal
  * contiguous parts: workgroup b reads part b % parts only.  On MI355X the
- * workgroups b, b + 8, ... of a launch run on one XCD, so with parts = 8 each
+ * workgroups b, b + 8, ... of a launch share one XCD, so with parts = 8 each
  * XCD re-reads its own part: a part larger than the XCD's 4 MB L2 inside a
  * buffer smaller than the 256 MB Infinity Cache measures the Infinity Cache
  * (the memory hierarchy levels of Sec. 2, Fig. 1).  bytes must be a multiple
@@ -375,8 +376,11 @@ mpk_status mpk_bw_probe_ex(const void *buf, uint64_t bytes, int32_t reps, int32_
 /* XCD placement: ids[b] (device, `workgroups` int32) receives the hardware
  * XCD index (XCC_ID register) of workgroup b of a launch of `workgroups`
  * 256-thread workgroups, each of which then sleeps `spin` rounds so that the
- * later ones are placed while the earlier ones still run.  The XCD-sliced
- * ticket streams (mpk_options.xcd_streams = 8) assume ids[b] = b % 8. */
+ * later ones are placed while the earlier ones still run.  Measured on
+ * MI355X: ids[b] = (b + r) % 8, the dispatcher continuing its round-robin
+ * over the XCDs from the previous launch (r = 0 in a fresh process).  The
+ * XCD-sliced ticket streams (mpk_options.xcd_streams = 8) need only that the
+ * workgroups b, b + 8, ... share an XCD. */
 mpk_status mpk_xcd_ids(int32_t *ids, int32_t workgroups, int64_t spin, void *stream);
 
 /* Latency of a point-to-point dependency hop (Sec. 4.3 replaces barriers by
