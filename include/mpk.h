@@ -415,6 +415,17 @@ mpk_status mpk_mlp_forward(const float *params, int32_t D, int32_t H, const floa
 mpk_status mpk_mlp_backward(const float *params, int32_t D, int32_t H, const float *X, const float *y, int32_t B,
                             const float *out, const float *cache, float *work, float *grads, float *loss,
                             void *stream);
+/* mpk_mlp_backward without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP stream capture, serving loops,
+ * harnesses that forbid hipMalloc): the B*(2H+1) floats of work live in a
+ * fixed per-GPU array of the library (16 MiB, held until the process ends),
+ * so the call allocates nothing.  B*(2H+1) must be <= 4194304 (MPK_ERR_ARG
+ * otherwise).  Same arguments and results as mpk_mlp_backward, bit for bit.
+ * All calls on one GPU share that array: calls that overlap on one GPU (on
+ * different streams or threads) race. */
+mpk_status mpk_mlp_backward_noalloc(const float *params, int32_t D, int32_t H, const float *X, const float *y,
+                                    int32_t B, const float *out, const float *cache, float *grads, float *loss,
+                                    void *stream);
 /* One Adam step (step = 1, 2, ...): m, v are the moment buffers (zero before
  * step 1), bias-corrected update params -= lr mhat / (sqrt(vhat) + eps). */
 mpk_status mpk_mlp_adam(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float beta1,

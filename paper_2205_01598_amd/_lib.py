@@ -110,6 +110,8 @@ SIGNATURES = {
     "mpk_mlp_forward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]),
     "mpk_mlp_backward": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P,
                                           _P, _P, _P]),
+    "mpk_mlp_backward_noalloc": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32, _P,
+                                                  _P, _P, _P, _P]),
     "mpk_mlp_adam": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
     "mpk_status_string": (ctypes.c_char_p, [ctypes.c_int32]),

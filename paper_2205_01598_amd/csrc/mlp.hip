@@ -19,11 +19,19 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "mpk_internal.h"
 
 using namespace mpk;
+
+// Scratch of the allocation-free backward pass (mpk_mlp_backward_noalloc):
+// the per-sample output gradient and hidden-layer gradients, B * (2H + 1)
+// floats, in a fixed device array instead of a caller workspace.  Every GPU
+// the library runs on holds its own copy (16 MiB) until the process ends.
+constexpr int64_t kMlpScratchFloats = int64_t(1) << 22;
+static __device__ __align__(256) float scratch[kMlpScratchFloats];
 
 namespace {
 
@@ -173,6 +181,30 @@ __global__ void mlp_adam(float *__restrict__ P, const float *__restrict__ G, flo
         if (e_ != hipSuccess) return fail(MPK_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Device address of `scratch` on each GPU, taken once per device with that
+// device current.  In host code the array's name is only a host-side stand-in,
+// so kernels and copies use these addresses, never the name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+mpk_status scratch_of_current_device(float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MPK_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPK_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MPK_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MPK_OK;
+}
+
 mpk_status check_dims(int32_t D, int32_t H, int32_t B) {
     if (D < 1 || D > 4096) return fail(MPK_ERR_ARG, "input width must be in [1, 4096]");
     if (H < 1 || H > kMaxHidden) return fail(MPK_ERR_ARG, "hidden width must be in [1, 256]");
@@ -220,6 +252,21 @@ mpk_status mpk_mlp_backward(const float *params, int32_t D, int32_t H, const flo
     if (loss) hipLaunchKernelGGL(mlp_loss, dim3(1), dim3(256), 0, s, B, y, out, loss);
     HIP_TRY(hipGetLastError());
     return MPK_OK;
+}
+
+mpk_status mpk_mlp_backward_noalloc(const float *params, int32_t D, int32_t H, const float *X, const float *y,
+                                    int32_t B, const float *out, const float *cache, float *grads, float *loss,
+                                    void *stream) {
+    mpk_status st = check_dims(D, H, B);
+    if (st != MPK_OK) return st;
+    if (B < 1) return fail(MPK_ERR_ARG, "empty batch");
+    if ((int64_t)B * (2 * H + 1) > kMlpScratchFloats)
+        return fail(MPK_ERR_ARG, "batch too large for the fixed scratch: B * (2H + 1) must be <= 4194304 floats");
+    float *work = nullptr;
+    if ((st = scratch_of_current_device(&work)) != MPK_OK) return st;
+    // every scratch entry the kernels read is written first in the same call,
+    // so nothing needs clearing
+    return mpk_mlp_backward(params, D, H, X, y, B, out, cache, work, grads, loss, stream);
 }
 
 mpk_status mpk_mlp_adam(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float beta1,
