@@ -262,6 +262,35 @@ __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restri
     }
 }
 
+// The gathers of a plain chunk (and, for k = 2 with the recurrence, the
+// epilogue operands of the calling thread's first output), issued without
+// waiting, so a caller may issue the next chunk's matrix loads behind them.
+template <typename VT, int K>
+struct ChunkGather {
+    typename AccumType<VT>::T xv[kProdPerThread];
+    Col2Ops pre;
+};
+
+template <typename VT, int K, bool REC, bool COH>
+__device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
+                                             int q, const double *__restrict__ yq2, const RecArgs &rec,
+                                             ChunkGather<VT, K> &gx) {
+    using AT = typename AccumType<VT>::T;
+    const int tid = threadIdx.x;
+    const int nr = d.y - d.x;
+#pragma unroll
+    for (int m = 0; m < kProdPerThread; ++m) gx.xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
+    gx.pre = Col2Ops{};
+    if constexpr (K == 2 && REC)
+        if (tid < nr * 2) gx.pre = col2_operands<COH>(d.x + (tid >> 1), tid & 1, x, yq2, q, rec);
+}
+
+template <typename VT, int K, bool REC, bool COH>
+__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K> &g, const ChunkGather<VT, K> &gx,
+                                             const double *__restrict__ x, double *__restrict__ y, int q,
+                                             const double *__restrict__ yq2, const RecArgs &rec,
+                                             ChunkLds<VT, K> &lds);
+
 // The rest of a plain chunk: gathers of x, products and row pointers to LDS,
 // then phase 2 (one thread per row for k = 1, per (row, column) for k >= 2,
 // stored order, four products read ahead) and the epilogue.
@@ -269,19 +298,23 @@ template <typename VT, int K, bool REC, bool COH>
 __device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
                                              double *__restrict__ y, int q, const double *__restrict__ yq2,
                                              const RecArgs &rec, ChunkLds<VT, K> &lds) {
+    ChunkGather<VT, K> gx;
+    chunk_gather<VT, K, REC, COH>(d, g, x, q, yq2, rec, gx);
+    chunk_reduce<VT, K, REC, COH>(d, g, gx, x, y, q, yq2, rec, lds);
+}
+
+template <typename VT, int K, bool REC, bool COH>
+__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K> &g, const ChunkGather<VT, K> &gx,
+                                             const double *__restrict__ x, double *__restrict__ y, int q,
+                                             const double *__restrict__ yq2, const RecArgs &rec,
+                                             ChunkLds<VT, K> &lds) {
     using AT = typename AccumType<VT>::T;
     constexpr int NP = kProdPerThread;
     const int tid = threadIdx.x;
     const int r0 = d.x, j0 = d.z;
     const int nr = d.y - d.x;
-    AT xv[NP];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
-    // k = 2 with the recurrence: the epilogue operands of this thread's first
-    // output travel with the gathers instead of after the sums
-    Col2Ops pre{};
-    if constexpr (K == 2 && REC)
-        if (tid < nr * 2) pre = col2_operands<COH>(r0 + (tid >> 1), tid & 1, x, yq2, q, rec);
+    const AT *xv = gx.xv;
+    const Col2Ops &pre = gx.pre;
 #pragma unroll
     for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
         if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = g.rbv[m];

@@ -50,7 +50,7 @@ struct mpk_plan {
     uint64_t device_bytes = 0;
     int32_t *d_rowptr = nullptr, *d_col = nullptr;
     void *d_val = nullptr;
-    int32_t *d_tile_row = nullptr, *d_work = nullptr;
+    int32_t *d_tile_row = nullptr, *d_trec = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_chunk = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;  // d_chunk: int4 per chunk
     int32_t *d_dep3x = nullptr;
@@ -212,7 +212,10 @@ struct MpkArgs {
     const void *val;
     const int32_t *tile_row;
     const int32_t *dep3;
-    const int32_t *work;
+    // tickets in stream order, two int4 each: (tile * 64 + q - 1, first
+    // chunk, end chunk, 0) and the first chunk's descriptor, so a workgroup
+    // reaches the matrix loads of its next ticket after one 32-byte read
+    const int4 *trec;
     int32_t n, ntiles, ntickets;
     const double *X;
     double *Y;
@@ -229,6 +232,19 @@ struct MpkArgs {
     int32_t dep_lists;
     int32_t p_run;  // powers computed (<= the plan's p); tickets of higher powers are skipped
 };
+
+// Element i of a table that no kernel writes while it runs (chunk
+// descriptors, dependency ranges), read through the constant address space
+// at a uniform index: a scalar load into scalar registers, counted apart
+// from the vector loads and stores.  A vector load would complete in order
+// behind the loads and write-through stores already issued, so waiting for
+// it would also wait for them; and the values are uniform, so the loops and
+// branches that use them stay uniform.
+typedef __attribute__((address_space(4))) const int32_t const_i32;
+__device__ __forceinline__ int4 table4(const int4 *tab, int i) {
+    const const_i32 *q = (const const_i32 *)tab + 4 * (int64_t)__builtin_amdgcn_readfirstlane(i);
+    return make_int4(q[0], q[1], q[2], q[3]);
+}
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -274,14 +290,16 @@ __device__ bool wait_flags(const uint32_t *f, int tile, const MpkArgs &a, int ti
     bool ok;
     if (a.dep_lists) {
         // a list holds few ranges: each is polled on its own
-        const int k0 = a.dep_ptr[tile], k1 = a.dep_ptr[tile + 1];
+        const int ut = __builtin_amdgcn_readfirstlane(tile);
+        const const_i32 *dp = (const const_i32 *)a.dep_ptr, *dr = (const const_i32 *)a.dep_rng;
+        const int k0 = dp[ut], k1 = dp[ut + 1];
         ok = true;
         for (int k = k0; k < k1 && ok; ++k) {
-            const int lo = a.dep_rng[2 * k], hi = a.dep_rng[2 * k + 1];
+            const int lo = dr[2 * (int64_t)k], hi = dr[2 * (int64_t)k + 1];
             ok = poll_flags(f, hi - lo + 1, [=](int i) { return lo + i; }, a, ticket, epoch);
         }
     } else {
-        const int32_t *d = a.dep3 + 6 * tile;
+        const const_i32 *d = (const const_i32 *)a.dep3 + 6 * (int64_t)__builtin_amdgcn_readfirstlane(tile);
         const int lo0 = d[0], lo1 = d[2], lo2 = d[4];
         const int n0 = max(0, d[1] - lo0 + 1), n1 = max(0, d[3] - lo1 + 1), n2 = max(0, d[5] - lo2 + 1);
         ok = poll_flags(
@@ -300,7 +318,7 @@ __device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
 }
 
 template <typename VT, int K, bool REC>
-__global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec) {
+__global__ __launch_bounds__(kBlock, 4) void mpk_persistent(MpkArgs a, RecArgs rec) {
     // The tickets form `nstreams` streams (1, or 8 XCD slices); workgroup b
     // serves stream b % nstreams.  Inside a stream the tickets are dealt over
     // S counters: sub-stripe s holds the stream's tickets s, s + S, ...;
@@ -314,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     __shared__ int s_sub, s_ok;
     __shared__ uint32_t s_epoch;
     __shared__ int s_next[2];
+    __shared__ int4 s_rec[2][2];  // the current and the next ticket record
     __shared__ ChunkLds<VT, K> lds;
     const int nS = a.nstreams;
     const int stream = blockIdx.x % nS;
@@ -348,24 +367,36 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
     // counter increments.
     auto next_ticket = [&](int t0, uint32_t &kk) -> int {
         int tn = t0;
-        while (tn < len && ((a.work[base + tn] & 63) + 1) > a.p_run) {
+        while (tn < len && ((a.trec[2 * (int64_t)(base + tn)].x & 63) + 1) > a.p_run) {
             kk = __hip_atomic_fetch_add(stripe_counter(a, counter), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tn = (int)min<int64_t>((int64_t)sub + (int64_t)kk * S, len);
         }
         return tn;
     };
-    if (threadIdx.x == 0 && a.p_run < MPK_MAX_POWER) {
+    if (threadIdx.x == 0) {
         uint32_t kk = 0;
-        s_next[0] = next_ticket(s_next[0], kk);
+        int t0 = s_next[0];
+        if (a.p_run < MPK_MAX_POWER) t0 = next_ticket(t0, kk);
+        if (t0 < len) {
+            s_rec[0][0] = a.trec[2 * (int64_t)(base + t0)];
+            s_rec[0][1] = a.trec[2 * (int64_t)(base + t0) + 1];
+        }
+        s_next[0] = t0;
     }
     __syncthreads();
     int t = s_next[0];
     for (int it = 1; t < len; ++it) {
-        const int w = a.work[base + t];
+        const int cur = (it - 1) & 1;
+        // the ticket is the same for the whole workgroup: kept in scalar
+        // registers, so the loops over its chunks are uniform
+        const int4 tr = s_rec[cur][0];
+        const int4 dl = s_rec[cur][1];
+        const int4 d0 = make_int4(__builtin_amdgcn_readfirstlane(dl.x), __builtin_amdgcn_readfirstlane(dl.y),
+                                  __builtin_amdgcn_readfirstlane(dl.z), __builtin_amdgcn_readfirstlane(dl.w));
+        const int w = __builtin_amdgcn_readfirstlane(tr.x);
         const int tile = w >> 6;
         const int q = (w & 63) + 1;
-        const int c0 = a.tile_chunk[tile], c1 = a.tile_chunk[tile + 1];
-        const int4 d0 = a.chunk[c0];
+        const int c0 = __builtin_amdgcn_readfirstlane(tr.y), c1 = __builtin_amdgcn_readfirstlane(tr.z);
         // The first chunk's matrix entries and row pointers do not depend on
         // the flags: they are loaded before the wait, so their latency and
         // the polling overlap.  The barriers around the poll order only LDS
@@ -387,12 +418,29 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         const double *xin = (q == 1) ? a.X : a.Y + (int64_t)(q - 2) * NK;
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
-        if (pre)
-            chunk_finish<VT, K, REC, true>(d0, g, xin, yout, q, yq2, rec, lds);
-        else
+        if constexpr (K <= 2) {
+            if (pre)
+                chunk_finish<VT, K, REC, true>(d0, g, xin, yout, q, yq2, rec, lds);
+            else
+                chunk_pass<VT, K, REC, true>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            // later chunks: each descriptor (a scalar load) is read while the
+            // chunk before it runs
+            int4 dn = table4(a.chunk, c0 + 1 < c1 ? c0 + 1 : c0);
+            for (int c = c0 + 1; c < c1; ++c) {
+                const int4 d = dn;
+                dn = table4(a.chunk, c + 1 < c1 ? c + 1 : c);
+                chunk_pass<VT, K, REC, true>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            }
+        } else {
             chunk_pass<VT, K, REC, true>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
-        for (int c = c0 + 1; c < c1; ++c)
-            chunk_pass<VT, K, REC, true>(a.chunk[c], a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            // later chunks: each descriptor is read while the chunk before it runs
+            int4 dn = table4(a.chunk, c0 + 1 < c1 ? c0 + 1 : c0);
+            for (int c = c0 + 1; c < c1; ++c) {
+                const int4 d = dn;
+                dn = table4(a.chunk, c + 1 < c1 ? c + 1 : c);
+                chunk_pass<VT, K, REC, true>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            }
+        }
         // The next ticket is taken only now: a workgroup never holds a ticket
         // it is not working on, so no ticket waits behind an idle one.
         uint32_t kn = 0;
@@ -405,6 +453,10 @@ __global__ __launch_bounds__(kBlock) void mpk_persistent(MpkArgs a, RecArgs rec)
         if (threadIdx.x == 0) {
             int tn = (int)min<int64_t>((int64_t)sub + (int64_t)kn * S, len);
             if (a.p_run < MPK_MAX_POWER) tn = next_ticket(tn, kn);
+            if (tn < len) {
+                s_rec[cur ^ 1][0] = a.trec[2 * (int64_t)(base + tn)];
+                s_rec[cur ^ 1][1] = a.trec[2 * (int64_t)(base + tn) + 1];
+            }
             s_next[it & 1] = tn;
         }
         __syncthreads();
@@ -858,11 +910,24 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_dep_rng, std::max<size_t>(h.dep_rng.size(), 2), &bytes)) != hipSuccess)
         return cleanup_fail(e, "deps");
-    if ((e = dev_alloc(al, &plan->d_work, W, &bytes)) != hipSuccess) return cleanup_fail(e, "work");
+    if ((e = dev_alloc(al, &plan->d_trec, 8 * W, &bytes)) != hipSuccess) return cleanup_fail(e, "tickets");
     if ((e = dev_alloc(al, &plan->d_flags, W, &bytes)) != hipSuccess) return cleanup_fail(e, "flags");
     if ((e = dev_alloc(al, &plan->d_ctrl, kCtrlWords, &bytes)) != hipSuccess) return cleanup_fail(e, "ctrl");
     if ((e = dev_alloc(al, &plan->d_perm, h.n, &bytes)) != hipSuccess) return cleanup_fail(e, "perm");
     const std::vector<int32_t> desc = chunk_descriptors(h.chunk_row, h.rowptr.data());
+    // ticket records in stream order: (ticket, first chunk, end chunk, 0,
+    // first chunk's descriptor)
+    std::vector<int32_t> trec(8 * (size_t)W);
+    for (int64_t i = 0; i < W; ++i) {
+        const int32_t w = h.work_streams[i], tile = w >> 6;
+        const int32_t c0 = h.tile_chunk[tile], c1 = h.tile_chunk[tile + 1];
+        int32_t *r = &trec[8 * (size_t)i];
+        r[0] = w;
+        r[1] = c0;
+        r[2] = c1;
+        r[3] = 0;
+        for (int m = 0; m < 4; ++m) r[4 + m] = desc[4 * (size_t)c0 + m];
+    }
     if ((e = dev_alloc(al, &plan->d_chunk, std::max<size_t>(desc.size(), 4), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
     if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
@@ -876,7 +941,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_dep3x, h.dep3x.data(), sizeof(int32_t) * 6 * T},
         {plan->d_dep_ptr, h.dep_ptr.data(), sizeof(int32_t) * h.dep_ptr.size()},
         {plan->d_dep_rng, h.dep_rng.data(), sizeof(int32_t) * h.dep_rng.size()},
-        {plan->d_work, h.work_streams.data(), sizeof(int32_t) * W},
+        {plan->d_trec, trec.data(), sizeof(int32_t) * 8 * W},
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
         {plan->d_chunk, desc.data(), sizeof(int32_t) * desc.size()},
         {plan->d_tile_chunk, h.tile_chunk.data(), sizeof(int32_t) * h.tile_chunk.size()},
@@ -986,7 +1051,7 @@ mpk_status mpk_run_first(mpk_plan *plan, int32_t powers, const double *X, double
     a.dep_ptr = plan->d_dep_ptr;
     a.dep_rng = plan->d_dep_rng;
     a.dep_lists = h.recursive ? 1 : 0;
-    a.work = plan->d_work;
+    a.trec = reinterpret_cast<const int4 *>(plan->d_trec);
     a.n = (int32_t)h.n;
     a.ntiles = (int32_t)h.dep_lo.size();
     a.ntickets = (int32_t)h.work.size();
