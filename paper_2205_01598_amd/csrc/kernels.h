@@ -268,7 +268,7 @@ __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restri
 template <typename VT, int K>
 struct ChunkGather {
     typename AccumType<VT>::T xv[kProdPerThread];
-    Col2Ops pre;
+    Col2Ops pre, pre2;  // epilogue operands of outputs tid and tid + kBlock (k = 2, recurrence)
 };
 
 template <typename VT, int K, bool REC, bool COH>
@@ -281,8 +281,15 @@ __device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K
 #pragma unroll
     for (int m = 0; m < kProdPerThread; ++m) gx.xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
     gx.pre = Col2Ops{};
-    if constexpr (K == 2 && REC)
+    gx.pre2 = Col2Ops{};
+    if constexpr (K == 2 && REC) {
+        // a chunk of up to 2048 / 2 nonzeros usually has at most 256 rows,
+        // i.e. at most two outputs per thread: both have their operands
+        // loaded here, so none is loaded after the row sums
         if (tid < nr * 2) gx.pre = col2_operands<COH>(d.x + (tid >> 1), tid & 1, x, yq2, q, rec);
+        if (tid + kBlock < nr * 2)
+            gx.pre2 = col2_operands<COH>(d.x + ((tid + kBlock) >> 1), tid & 1, x, yq2, q, rec);
+    }
 }
 
 template <typename VT, int K, bool REC, bool COH>
@@ -314,7 +321,7 @@ __device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K
     const int r0 = d.x, j0 = d.z;
     const int nr = d.y - d.x;
     const AT *xv = gx.xv;
-    const Col2Ops &pre = gx.pre;
+    const Col2Ops &pre = gx.pre, &pre2 = gx.pre2;
 #pragma unroll
     for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
         if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = g.rbv[m];
@@ -341,7 +348,8 @@ __device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K
             }
             for (; i < e; ++i) sum = sum + lds.prod[i * 2 + c];
             Col2Ops op{};
-            if constexpr (REC) op = o == tid ? pre : col2_operands<COH>(r0 + r, c, x, yq2, q, rec);
+            if constexpr (REC)
+                op = o == tid ? pre : o == tid + kBlock ? pre2 : col2_operands<COH>(r0 + r, c, x, yq2, q, rec);
             store_col2<REC, COH>(r0 + r, c, (double)sum, op, y, q, rec);
         }
     } else if constexpr (K == 1) {
