@@ -112,12 +112,51 @@ def time_run(torch, plan: Plan, X, Y, reps: int = 5, warmup: int = 2) -> float:
     return s.elapsed_time(e) / reps
 
 
-def sweep(seeds, db_path: str, p_list=(4, 8), n_min=1e5, n_max=1e6, log=print):
-    """Exhaustive sweep over ``config_grid()`` for every seed not yet in the
-    database; appends records and flushes after every matrix."""
-    import torch
-
+def _corpus_matrix(args):
     import workloads as W
+
+    return W.tuner_matrix(*args)
+
+
+def _corpus(seeds, n_min, n_max, workers):
+    """(seed, matrix, spec) in seed order; with ``workers`` > 0 the matrices
+    are generated that many seeds ahead in worker processes (no GPU use
+    there), so generation overlaps the timing of the previous matrix."""
+    if workers <= 0:
+        import workloads as W
+
+        for seed in seeds:
+            yield (seed,) + tuple(W.tuner_matrix(seed, n_min, n_max))
+        return
+    import collections
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        pending = collections.deque()
+        it = iter(seeds)
+        for seed in it:
+            pending.append((seed, ex.submit(_corpus_matrix, (seed, n_min, n_max))))
+            if len(pending) >= workers:
+                break
+        while pending:
+            seed, fut = pending.popleft()
+            nxt = next(it, None)
+            if nxt is not None:
+                pending.append((nxt, ex.submit(_corpus_matrix, (nxt, n_min, n_max))))
+            A, spec = fut.result()
+            yield seed, A, spec
+
+
+def sweep(seeds, db_path: str, p_list=(4, 8), n_min=1e5, n_max=1e6, log=print, workers=0,
+          time_limit=None):
+    """Exhaustive sweep over ``config_grid()`` for every seed not yet in the
+    database; appends records and flushes after every matrix.  ``workers``
+    processes generate the next matrices meanwhile.  With ``time_limit``
+    (seconds) no new matrix is started once that much time has passed; a
+    later call with the same database continues where this one stopped."""
+    start = time.time()
+    import torch
 
     done = set()
     if os.path.exists(db_path):
@@ -126,11 +165,11 @@ def sweep(seeds, db_path: str, p_list=(4, 8), n_min=1e5, n_max=1e6, log=print):
                 done.add(json.loads(line)["seed"])
     dev = torch.device("cuda:0")
     grid = config_grid()
-    for seed in seeds:
-        if seed in done:
-            continue
-        t0 = time.time()
-        A, spec = W.tuner_matrix(seed, n_min, n_max)
+    t0 = time.time()
+    for seed, A, spec in _corpus([s for s in seeds if s not in done], n_min, n_max, workers):
+        if time_limit is not None and time.time() - start > time_limit:
+            log(f"time limit reached before seed {seed}")
+            break
         plan = Plan(A, max(p_list), 256 << 20, root_mode=1)
         perm = plan.arrays()[0].astype(np.int64)
         x = np.random.default_rng(seed).uniform(-1, 1, A.n)
@@ -153,7 +192,8 @@ def sweep(seeds, db_path: str, p_list=(4, 8), n_min=1e5, n_max=1e6, log=print):
         dflt = [r["ms"] for r in recs if r["p"] == max(p_list) and r["config"] == DEFAULT][0]
         log(f"seed {seed} {spec['family']} n={spec['n']} nnz={spec['nnz']}: default {dflt:.3f} ms, "
             f"best {best:.3f} ms ({time.time() - t0:.1f}s)")
-        del plan, X
+        t0 = time.time()
+        del plan, X, A
 
 
 def load_db(path: str):
@@ -414,8 +454,9 @@ def evaluate(tuner: LearnedTuner, records, static=None, shortlist=(3,)):
 
 
 def main(argv=None):
-    """``sweep FIRST LAST OUT [N_MAX]``: time every configuration on the
-    corpus seeds FIRST..LAST-1 (GPU), appending to OUT.
+    """``sweep FIRST LAST OUT [--n-max N] [--workers W] [--time-limit S]``:
+    time every configuration on the corpus seeds FIRST..LAST-1 (GPU),
+    appending to OUT (seeds already in OUT are skipped).
     ``compact OUT IN...``: merge sweep files into the compact database."""
     import argparse
 
@@ -425,13 +466,16 @@ def main(argv=None):
     s1.add_argument("first", type=int)
     s1.add_argument("last", type=int)
     s1.add_argument("out")
-    s1.add_argument("--n-max", type=float, default=4e6)
+    s1.add_argument("--n-max", type=float, default=1e7)
+    s1.add_argument("--workers", type=int, default=2)
+    s1.add_argument("--time-limit", type=float, default=None)
     s2 = sub.add_parser("compact")
     s2.add_argument("out")
     s2.add_argument("inputs", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        sweep(range(a.first, a.last), a.out, n_max=a.n_max, log=lambda m: print(m, flush=True))
+        sweep(range(a.first, a.last), a.out, n_max=a.n_max, workers=a.workers, time_limit=a.time_limit,
+              log=lambda m: print(m, flush=True))
     else:
         recs = []
         for f in a.inputs:

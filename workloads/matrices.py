@@ -303,6 +303,14 @@ def anderson_3d(n: int, W: float = 16.0, t: float = -1.0, seed: int = 0,
 # irregular matrices
 # ----------------------------------------------------------------------------
 
+def _row_major_order(rows: np.ndarray, cols: np.ndarray, n: int) -> np.ndarray:
+    """Permutation that sorts entries by (row, column), ties in input order:
+    the order of ``np.lexsort((cols, rows))`` for 0 <= rows, cols < n, from
+    one stable sort of a combined int64 key (an order of magnitude faster on
+    10^8 entries)."""
+    return np.argsort(rows.astype(np.int64) * int(n) + cols.astype(np.int64), kind="stable")
+
+
 def random_geometric(N: int, avg_degree: float = 16.0, seed: int = 0,
                      radius: float | None = None):
     """Random geometric graph: N points U[0,1]^3, edge when distance < r.
@@ -322,7 +330,7 @@ def random_geometric(N: int, avg_degree: float = 16.0, seed: int = 0,
     tree = cKDTree(pts)
     pairs = tree.query_pairs(radius, output_type="ndarray").astype(np.int64)
     if pairs.size:
-        order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+        order = _row_major_order(pairs[:, 0], pairs[:, 1], N)
         pairs = pairs[order]
     w = 1.0 - rng_val.random(pairs.shape[0])
     rows = np.concatenate([pairs[:, 0], pairs[:, 1]])
@@ -333,7 +341,7 @@ def random_geometric(N: int, avg_degree: float = 16.0, seed: int = 0,
     rows = np.concatenate([rows, iso])
     cols = np.concatenate([cols, iso])
     ww = np.concatenate([ww, np.ones(iso.size)])
-    order = np.lexsort((cols, rows))
+    order = _row_major_order(rows, cols, N)
     rows, cols, ww = rows[order], cols[order], ww[order]
     rowsum = np.bincount(rows, weights=ww, minlength=N)
     vals = ww / rowsum[rows]
@@ -398,7 +406,7 @@ def zipf_rows(n: int, exponent: float, seed: int = 0, cap: int = 1024) -> CSR:
     rows = np.concatenate([rows, np.arange(n)])
     cols = np.concatenate([cols, np.arange(n)])
     vals = np.concatenate([vals, np.zeros(n)])
-    order = np.lexsort((cols, rows))
+    order = _row_major_order(rows, cols, n)
     rows, cols, vals = rows[order], cols[order], vals[order]
     keep = np.ones(rows.size, dtype=bool)
     keep[1:] = (rows[1:] != rows[:-1]) | (cols[1:] != cols[:-1])
@@ -433,7 +441,7 @@ def random_small_csr(n: int, density: float, rng: np.random.Generator,
         v = rng.integers(-2, 3, size=r.size).astype(np.float64)
     else:
         v = rng.uniform(-1.0, 1.0, size=r.size)
-    order = np.lexsort((c, r))
+    order = _row_major_order(r, c, n)
     r, c, v = r[order], c[order], v[order]
     rowptr = np.zeros(n + 1, dtype=np.int64)
     if n:
@@ -455,7 +463,7 @@ def relabel(csr: CSR, new2old: np.ndarray) -> CSR:
     rows = np.repeat(np.arange(n), lens)
     cols = old2new[csr.col[src].astype(np.int64)]
     vals = csr.val[src]
-    order = np.lexsort((cols, rows))
+    order = _row_major_order(rows, cols, n)
     return CSR(n, rowptr, cols[order].astype(np.int32), vals[order].copy())
 
 
@@ -501,7 +509,7 @@ def _random_valued(csr: CSR, rng) -> CSR:
         miss = np.nonzero(~has_diag)[0]
         rows = np.concatenate([rows, miss])
         cols = np.concatenate([csr.col.astype(np.int64), miss])
-        order = np.lexsort((cols, rows))
+        order = _row_major_order(rows, cols, n)
         rows, cols = rows[order], cols[order]
         rowptr = np.zeros(n + 1, np.int64)
         np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
