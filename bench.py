@@ -206,6 +206,13 @@ def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
                "gflops": round(2.0 * A.nnz * 2 * M / tm / 1e6, 1),
                "config": cfg, "bit_equal_to_baseline": bool(torch.equal(acc, acc_base))}
         if dt == "f64":
+            # the fixed cost of the persistent kernel: one level group (no
+            # reuse window), then back to the pick
+            pl.retune(p, 64 << 30, root_mode=1, nrhs=2, val_dtype=dt, skew=2, tile_nnz=8192)
+            ent["one_level_group"] = {"groups": pl.info()["n_groups"],
+                                      "step_ms": round(timed(torch, lambda: prop.step(X, acc), 20, 3), 4)}
+            pl.status()
+            tune.autotune(torch, pl, p, [cfg], lambda: prop.step(X, acc), reps=1, warmup=0, nrhs=2, val_dtype=dt)
             # the working set fits the 256 MB Infinity Cache: also time each
             # step after reading 512 MB of other data
             scrub = torch.ones(64 << 20, dtype=torch.float64, device=dev)
@@ -581,6 +588,13 @@ def main():
               "launch_per_node_ms": round(timed(torch, lambda: plan.run_sync(X, Y, "node"), 3, 1), 4),
               "launch_per_wavefront_ms": round(timed(torch, lambda: plan.run_sync(X, Y, "wavefront"), 5, 1), 4),
               "p2p_flags_ms": round(ms, 4), "baseline_ms": round(t_base, 4)}
+    # the persistent kernel's fixed cost: the same kernel with a budget that
+    # puts every level in one group (no reuse window), then back to the pick
+    plan.retune(p, 64 << 30, root_mode=1, skew=2, tile_nnz=int(cfg.get("tile_nnz", 8192)))
+    ladder["one_level_group"] = {"groups": plan.info()["n_groups"],
+                                 "ms": round(timed(torch, lambda: plan.run(X, Y), 10, 2), 4)}
+    plan.status()
+    tune.autotune(torch, plan, p, [cfg], lambda: plan.run(X, Y), reps=1, warmup=0)
     log(f"sync ladder: {ladder}")
 
     # ---- CPU oracle (FP64; all host threads and one) -----------------------------------
