@@ -538,6 +538,25 @@ def main():
     X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
     X0 = torch.from_numpy(x).to(dev)
     Y = torch.empty((p, n), dtype=torch.float64, device=dev)
+    # the same plan from the CSR in device memory, which stays there (up to
+    # a plan ready to run); its run equals the host plan's bit for bit
+    dA = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (A.rowptr, A.col, A.val)]
+    resident = {}
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        pres = Plan.from_device(*dA, p, 256 << 20, root_mode=1)
+        torch.cuda.synchronize()
+        resident["seconds"] = min(resident.get("seconds", 1e9), time.time() - t0)
+    assert np.array_equal(pres.arrays()[0], plan.arrays()[0])
+    Yr = torch.empty_like(Y)
+    pres.run(X, Yr)
+    plan.run(X, Y)
+    pres.status()
+    resident["bit_equal_to_host_plan_run"] = bool(torch.equal(Yr, Y))
+    resident["phase_seconds"] = [round(v, 4) for v in pres.info()["phase_seconds"]]
+    del pres, Yr, dA
+    log(f"resident plan: {resident}")
     flop = 2.0 * nnz * p
 
     # ---- baselines: p back-to-back SpMV launches ------------------------------
@@ -779,6 +798,10 @@ def main():
         "plan_seconds": round(plan_s, 2),
         "plan_spmv_equivalents": round(plan_s / (t_base / p * 1e-3), 0),
         "plan_seconds_plan_on_device": round(plan_dev_s, 2),
+        "plan_device_resident": {"seconds": round(resident["seconds"], 4),
+                                 "spmv_equivalents": round(resident["seconds"] / (t_base / p * 1e-3), 0),
+                                 "phase_seconds": resident["phase_seconds"],
+                                 "bit_equal_to_host_plan_run": resident["bit_equal_to_host_plan_run"]},
         "plan_phase_seconds": plan_phases,
         "sync_ladder": ladder,
         "recursion": recursion,

@@ -201,6 +201,27 @@ void mpk_options_default(mpk_options *opt);
 mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            const mpk_options *opt, mpk_plan **out);
 
+/* Preprocessing of a matrix that is already in GPU memory, which stays there
+ * (the preprocessing of Sec. 6, kept next to the matrix: no copy of the CSR
+ * to the host and back).  A->rowptr (int64, n+1), A->col and A->val are
+ * device pointers on the current GPU; n and nnz are host values.  The CSR is
+ * validated on the device with the checks of mpk_plan_create; then graph,
+ * root search and BFS levels (Eq. 3), the renumbering (Sec. 4.1) and P A P^T
+ * run on the GPU as with opt->plan_on_device = 1, with the same results bit
+ * for bit, and the level groups, schedule and tiles are built as by
+ * mpk_plan_create.  The plan keeps P A P^T in device memory (FP64, about
+ * 12 bytes per nonzero plus the row pointers; FP32/BF16 values are
+ * converted on the device at upload) and only the row pointers, permutation
+ * and levels on the host; mpk_plan_matrix copies the matrix back on demand.
+ * The caller's CSR is only read and may be freed on return.
+ * Restrictions: rows sorted by column with a symmetric pattern and at most
+ * 4096 stored entries per row, and recursion_stages = 0 (refinement runs on
+ * the host); other matrices are planned with mpk_plan_create.
+ * Errors: MPK_ERR_ARG, MPK_ERR_CSR, MPK_ERR_OOM, MPK_ERR_HIP,
+ * MPK_ERR_UNSUPPORTED (the restrictions above, nnz >= 2^31 or n >= 2^31). */
+mpk_status mpk_plan_create_device(const mpk_csr *A, int32_t p, uint64_t cache_bytes, const mpk_options *opt,
+                                  mpk_plan **out);
+
 /* Re-derives the level groups, schedule, tiles and tickets for a new p, cache
  * budget C and options, keeping the BFS levels and the renumbered matrix (the
  * expensive part of preprocessing; Sec. 5 notes that p_m and C do not change

@@ -78,6 +78,8 @@ SIGNATURES = {
     "mpk_options_default": (None, [ctypes.POINTER(mpk_options)]),
     "mpk_plan_create": (ctypes.c_int32, [ctypes.POINTER(mpk_csr), ctypes.c_int32, ctypes.c_uint64,
                                          ctypes.POINTER(mpk_options), ctypes.POINTER(_P)]),
+    "mpk_plan_create_device": (ctypes.c_int32, [ctypes.POINTER(mpk_csr), ctypes.c_int32, ctypes.c_uint64,
+                                         ctypes.POINTER(mpk_options), ctypes.POINTER(_P)]),
     "mpk_plan_retune": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(mpk_options)]),
     "mpk_plan_query": (ctypes.c_int32, [_P, ctypes.POINTER(mpk_plan_info)]),
     "mpk_plan_arrays": (ctypes.c_int32, [_P, _I32P, _I32P, _I32P, _I32P]),

@@ -57,6 +57,10 @@ struct mpk_plan {
     int32_t *d_dep_ptr = nullptr, *d_dep_rng = nullptr;  // refined plans: per-tile range lists
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
     std::vector<void *> allocs;
+    // plans made from device memory: P A P^T kept on the GPU (FP64 values)
+    // for the plan's lifetime, shared by every upload after a retune
+    bool resident = false;
+    ResidentMatrix rm;
 };
 
 struct mpk_spmv {
@@ -143,6 +147,52 @@ void convert_values(const double *src, size_t n, int32_t dtype, std::vector<uint
     } else {
         uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
         for (size_t i = 0; i < n; ++i) o[i] = f32_to_bf16_bits((float)src[i]);
+    }
+}
+
+// The same conversions on the device for a matrix that stays there, in
+// integer arithmetic so the result does not depend on the device's rounding
+// or denormal modes: f64 -> f32 rounds to nearest even (overflow to
+// infinity, subnormal results kept, a NaN keeps its sign and upper payload
+// bits and becomes quiet, as the host's conversion does), then bf16 as
+// f32_to_bf16_bits.
+__device__ __forceinline__ uint32_t f64_to_f32_bits(uint64_t u) {
+    const uint32_t sign = (uint32_t)(u >> 63) << 31;
+    const int32_t ex = (int32_t)((u >> 52) & 0x7ff);
+    const uint64_t man = u & ((uint64_t(1) << 52) - 1);
+    if (ex == 0x7ff) return man ? sign | 0x7fc00000u | (uint32_t)(man >> 29) : sign | 0x7f800000u;
+    const int32_t e = ex - 1023 + 127;
+    if (e >= 255) return sign | 0x7f800000u;
+    if (e >= 1) {
+        uint32_t r = ((uint32_t)e << 23) | (uint32_t)(man >> 29);
+        const uint64_t rem = man & ((uint64_t(1) << 29) - 1), half = uint64_t(1) << 28;
+        if (rem > half || (rem == half && (r & 1u))) ++r;  // a carry moves into the exponent (or to infinity)
+        return sign | r;
+    }
+    if (ex == 0) return sign;  // FP64 subnormals are far below the FP32 range
+    // FP32 subnormal or zero: the value in units of 2^-149 is full * 2^(ex - 926)
+    const uint64_t full = (uint64_t(1) << 52) | man;
+    const int32_t sh = 926 - ex;  // >= 30 here
+    if (sh >= 54) return sign;    // below half the smallest subnormal
+    uint32_t r = (uint32_t)(full >> sh);
+    const uint64_t rem = full & ((uint64_t(1) << sh) - 1), half = uint64_t(1) << (sh - 1);
+    if (rem > half || (rem == half && (r & 1u))) ++r;
+    return sign | r;
+}
+
+__device__ __forceinline__ uint16_t f32_bits_to_bf16(uint32_t u) {
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
+    const uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + rounding) >> 16);
+}
+
+__global__ void convert_values_kernel(const double *__restrict__ src, int64_t n, int32_t dtype, void *dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t f = f64_to_f32_bits((uint64_t)__double_as_longlong(src[i]));
+        if (dtype == MPK_F32)
+            static_cast<uint32_t *>(dst)[i] = f;
+        else
+            static_cast<uint16_t *>(dst)[i] = f32_bits_to_bf16(f);
     }
 }
 
@@ -756,6 +806,29 @@ mpk_status mpk_plan_create(const mpk_csr *A, int32_t p, uint64_t cache_bytes, co
     return MPK_OK;
 }
 
+mpk_status mpk_plan_create_device(const mpk_csr *A, int32_t p, uint64_t cache_bytes, const mpk_options *opt,
+                                  mpk_plan **out) {
+    if (!out) return fail(MPK_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    mpk_options o;
+    mpk_options_default(&o);
+    if (opt) {
+        if (opt->size != sizeof(mpk_options)) return fail(MPK_ERR_ARG, "mpk_options.size mismatch");
+        o = *opt;
+    }
+    if (!supported(o.val_dtype, o.nrhs, false)) return fail(MPK_ERR_UNSUPPORTED, "nrhs/dtype combination");
+    mpk_plan *plan = new (std::nothrow) mpk_plan();
+    if (!plan) return fail(MPK_ERR_OOM, "host allocation failed");
+    plan->resident = true;
+    mpk_status st = build_resident_plan(A, p, cache_bytes, o, plan->hp, &plan->rm);
+    if (st != MPK_OK) {
+        mpk_plan_destroy(plan);
+        return st;
+    }
+    *out = plan;
+    return MPK_OK;
+}
+
 mpk_status mpk_plan_retune(mpk_plan *plan, int32_t p, uint64_t cache_bytes, const mpk_options *opt) {
     if (!plan) return fail(MPK_ERR_ARG, "null plan");
     mpk_options o;
@@ -849,6 +922,11 @@ mpk_status mpk_plan_matrix(const mpk_plan *plan, int64_t *rowptr, int32_t *col, 
     const HostPlan &h = plan->hp;
     if (rowptr)
         for (size_t i = 0; i < h.rowptr.size(); ++i) rowptr[i] = h.rowptr[i];
+    if (plan->resident) {
+        if (col && h.nnz > 0) HIP_TRY(hipMemcpy(col, plan->rm.col, sizeof(int32_t) * h.nnz, hipMemcpyDeviceToHost));
+        if (val && h.nnz > 0) HIP_TRY(hipMemcpy(val, plan->rm.val, sizeof(double) * h.nnz, hipMemcpyDeviceToHost));
+        return MPK_OK;
+    }
     if (col) std::copy(h.col.begin(), h.col.end(), col);
     if (val) std::copy(h.val.begin(), h.val.end(), val);
     return MPK_OK;
@@ -889,7 +967,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     const int64_t T = (int64_t)h.dep_lo.size();
     const int64_t W = (int64_t)h.work.size();
     std::vector<uint8_t> vbuf;
-    convert_values(h.val.data(), h.val.size(), h.opt.val_dtype, vbuf);
+    if (!plan->resident) convert_values(h.val.data(), h.val.size(), h.opt.val_dtype, vbuf);
     uint64_t bytes = 0;
     auto &al = plan->allocs;
     auto cleanup_fail = [&](hipError_t e, const char *what) {
@@ -898,11 +976,32 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
                     std::string(what) + ": " + hipGetErrorString(e));
     };
     hipError_t e;
-    if ((e = dev_alloc(al, &plan->d_rowptr, h.n + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "rowptr");
-    if ((e = dev_alloc(al, &plan->d_col, h.nnz, &bytes)) != hipSuccess) return cleanup_fail(e, "col");
-    uint8_t *dv = nullptr;
-    if ((e = dev_alloc(al, &dv, vbuf.size(), &bytes)) != hipSuccess) return cleanup_fail(e, "val");
-    plan->d_val = dv;
+    if (plan->resident) {
+        // the renumbered matrix is already on the device; FP32 / BF16 values
+        // are converted there
+        bytes += sizeof(int32_t) * (uint64_t)(h.n + 1) + (sizeof(int32_t) + sizeof(double)) * (uint64_t)h.nnz;
+        plan->d_rowptr = plan->rm.rowptr;
+        plan->d_col = plan->rm.col;
+        if (h.opt.val_dtype == MPK_F64) {
+            plan->d_val = plan->rm.val;
+        } else {
+            uint8_t *dv = nullptr;
+            if ((e = dev_alloc(al, &dv, (size_t)h.nnz * value_bytes(h.opt.val_dtype), &bytes)) != hipSuccess)
+                return cleanup_fail(e, "val");
+            plan->d_val = dv;
+            if (h.nnz > 0) {
+                hipLaunchKernelGGL(convert_values_kernel, dim3(2048), dim3(256), 0, 0, plan->rm.val, h.nnz,
+                                   h.opt.val_dtype, dv);
+                if ((e = hipGetLastError()) != hipSuccess) return cleanup_fail(e, "value conversion");
+            }
+        }
+    } else {
+        if ((e = dev_alloc(al, &plan->d_rowptr, h.n + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "rowptr");
+        if ((e = dev_alloc(al, &plan->d_col, h.nnz, &bytes)) != hipSuccess) return cleanup_fail(e, "col");
+        uint8_t *dv = nullptr;
+        if ((e = dev_alloc(al, &dv, vbuf.size(), &bytes)) != hipSuccess) return cleanup_fail(e, "val");
+        plan->d_val = dv;
+    }
     if ((e = dev_alloc(al, &plan->d_tile_row, T + 1, &bytes)) != hipSuccess) return cleanup_fail(e, "tiles");
     if ((e = dev_alloc(al, &plan->d_dep3, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
     if ((e = dev_alloc(al, &plan->d_dep3x, 6 * T, &bytes)) != hipSuccess) return cleanup_fail(e, "deps");
@@ -933,9 +1032,9 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
     struct Cp { void *d; const void *s; size_t b; } cps[] = {
-        {plan->d_rowptr, h.rowptr.data(), sizeof(int32_t) * (h.n + 1)},
-        {plan->d_col, h.col.data(), sizeof(int32_t) * h.nnz},
-        {plan->d_val, vbuf.data(), h.nnz * value_bytes(h.opt.val_dtype)},
+        {plan->d_rowptr, h.rowptr.data(), plan->resident ? 0 : sizeof(int32_t) * (h.n + 1)},
+        {plan->d_col, h.col.data(), plan->resident ? 0 : sizeof(int32_t) * h.nnz},
+        {plan->d_val, vbuf.data(), plan->resident ? 0 : h.nnz * value_bytes(h.opt.val_dtype)},
         {plan->d_tile_row, h.tile_row.data(), sizeof(int32_t) * (T + 1)},
         {plan->d_dep3, h.dep3.data(), sizeof(int32_t) * 6 * T},
         {plan->d_dep3x, h.dep3x.data(), sizeof(int32_t) * 6 * T},
@@ -1179,6 +1278,11 @@ mpk_status mpk_plan_status(mpk_plan *plan, void *stream) {
 void mpk_plan_destroy(mpk_plan *plan) {
     if (!plan) return;
     free_all(plan->allocs);
+    if (plan->resident) {
+        (void)hipFree(plan->rm.rowptr);
+        (void)hipFree(plan->rm.col);
+        (void)hipFree(plan->rm.val);
+    }
     delete plan;
 }
 

@@ -56,6 +56,12 @@ struct HostPlan {
     std::vector<int32_t> chunk_row;  // n_chunks+1: kernel work units inside tiles
     std::vector<int32_t> tile_chunk; // n_tiles+1
 
+    // Plans created from a CSR in device memory keep P A P^T on the GPU only:
+    // col and val above stay empty, rowptr is the host copy of the device row
+    // pointers, and the tile dependencies are found on the device.
+    const int32_t *dev_rowptr = nullptr;  // device, n+1
+    const int32_t *dev_col = nullptr;     // device, nnz
+
     int64_t max_level_rows = 0, max_group_nnz = 0, violating_groups = 0;
     int32_t tile_nnz = 0;
     double plan_seconds = 0.0;
@@ -80,6 +86,21 @@ void restore_schedule(HostPlan &hp, ScheduleState &s);  // moves them back
 // Runs every host step of the plan.  Returns MPK_OK or an error (message set).
 mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                            const mpk_options &opt, HostPlan &hp);
+
+// The renumbered matrix P A P^T of a plan made from device memory, in device
+// memory allocated with hipMalloc (freed with hipFree by its owner).
+struct ResidentMatrix {
+    int32_t *rowptr = nullptr;  // n+1
+    int32_t *col = nullptr;     // nnz
+    double *val = nullptr;      // nnz, FP64
+};
+
+// The plan of a CSR whose rowptr/col/val are device pointers on the current
+// GPU (rows sorted, pattern symmetric): graph, levels and P A P^T on the GPU
+// (device_plan_resident), then the schedule; M receives the device matrix
+// and hp.dev_rowptr/dev_col point into it.
+mpk_status build_resident_plan(const mpk_csr *A_dev, int32_t p, uint64_t cache_bytes, const mpk_options &opt,
+                               HostPlan &hp, ResidentMatrix *M);
 
 // The part of the plan that depends on p, the cache budget and the launch
 // options (level groups, schedule, tiles, dependencies, tickets); reuses the
@@ -121,6 +142,28 @@ mpk_status device_bfs_levels(int64_t n, const int64_t *ptr, const int32_t *adj, 
 mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, std::vector<int32_t> &perm,
                        std::vector<int32_t> &level_ptr, std::vector<int32_t> &rowptr, std::vector<int32_t> &col,
                        std::vector<double> &val, bool *handled, double *phase_seconds);
+
+// Graph, levels and P A P^T on the current GPU for a CSR already in device
+// memory (plan_device.hip).  The CSR is validated on the device
+// (MPK_ERR_CSR); rows must be sorted with a symmetric pattern, and no row of
+// A may hold more than kResidentRowMax entries (MPK_ERR_UNSUPPORTED).  Host
+// copies of perm, level_ptr and the new row pointers; M receives the device
+// matrix (on error nothing is left allocated).  phase_seconds[0..2]: graph,
+// levels, renumbering.
+constexpr int64_t kResidentRowMax = 4096;
+mpk_status device_plan_resident(const mpk_csr *A_dev, int32_t root_mode, int64_t *root_out,
+                                std::vector<int32_t> &perm, std::vector<int32_t> &level_ptr,
+                                std::vector<int32_t> &rowptr, ResidentMatrix *M, double *phase_seconds);
+
+// For every tile t (rows [tile_row[t], tile_row[t+1]) of group g =
+// tile_group[t]) and m = 0, 1, 2: the smallest and largest column the tile
+// reads among the rows [group_row[g-1+m], group_row[g+m]) of group g-1+m,
+// from the device matrix (rowptr, col): out[6t+2m] = smallest (INT32_MAX if
+// none), out[6t+2m+1] = largest (-1 if none).  *bad = true if a column lies
+// outside the three groups.
+mpk_status device_tile_columns(const int32_t *d_rowptr, const int32_t *d_col, const std::vector<int32_t> &tile_row,
+                               const std::vector<int32_t> &tile_group, const std::vector<int32_t> &group_row,
+                               std::vector<int32_t> &out, bool *bad);
 
 // Bytes per stored nonzero for Eq. (5): value bytes + 4 (int32 column).
 int32_t bytes_per_nnz(int32_t dtype);

@@ -711,6 +711,16 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         auto tile_of = [&](int64_t row) -> int64_t {
             return std::upper_bound(hp.tile_row.begin(), hp.tile_row.end(), (int32_t)row) - hp.tile_row.begin() - 1;
         };
+        // a matrix kept on the device: the column extremes per tile and
+        // neighbouring group come from the device (same definition)
+        std::vector<int32_t> dev_cols;
+        if (hp.dev_col != nullptr) {
+            std::vector<int32_t> group_row(G + 1);
+            for (int64_t gi = 0; gi <= G; ++gi) group_row[gi] = hp.level_ptr[hp.group_ptr[gi]];
+            mpk_status st = device_tile_columns(hp.dev_rowptr, hp.dev_col, hp.tile_row, hp.tile_group, group_row,
+                                                dev_cols, &bad);
+            if (st != MPK_OK) return st;
+        }
 #pragma omp parallel for schedule(dynamic, 16) reduction(|| : bad)
         for (int64_t t = 0; t < T; ++t) {
             const int64_t gi = hp.tile_group[t];
@@ -725,17 +735,25 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
             }
             lo[1] = r0;
             hi[1] = r1 - 1;
-            for (int64_t j = hp.rowptr[r0]; j < hp.rowptr[r1]; ++j) {
-                const int64_t c = hp.col[j];
-                int m = -1;
-                for (int mm = 0; mm < 3; ++mm)
-                    if (c >= gstart[mm] && c < gend[mm]) m = mm;
-                if (m < 0) {
-                    bad = true;
-                    continue;
+            if (!dev_cols.empty()) {
+                for (int m = 0; m < 3; ++m)
+                    if (dev_cols[6 * t + 2 * m + 1] >= 0) {
+                        lo[m] = std::min<int64_t>(lo[m], dev_cols[6 * t + 2 * m]);
+                        hi[m] = std::max<int64_t>(hi[m], dev_cols[6 * t + 2 * m + 1]);
+                    }
+            } else {
+                for (int64_t j = hp.rowptr[r0]; j < hp.rowptr[r1]; ++j) {
+                    const int64_t c = hp.col[j];
+                    int m = -1;
+                    for (int mm = 0; mm < 3; ++mm)
+                        if (c >= gstart[mm] && c < gend[mm]) m = mm;
+                    if (m < 0) {
+                        bad = true;
+                        continue;
+                    }
+                    lo[m] = std::min(lo[m], c);
+                    hi[m] = std::max(hi[m], c);
                 }
-                lo[m] = std::min(lo[m], c);
-                hi[m] = std::max(hi[m], c);
             }
             int64_t all_lo = std::numeric_limits<int64_t>::max(), all_hi = -1;
             for (int m = 0; m < 3; ++m) {
@@ -922,11 +940,9 @@ void plan_features(const HostPlan &hp, double *f) {
     }
 }
 
-mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
-                           const mpk_options &opt, HostPlan &hp) {
-    auto t0 = std::chrono::steady_clock::now();
-    mpk_status st = validate_csr(A);
-    if (st != MPK_OK) return st;
+namespace {
+
+mpk_status check_create_options(int32_t p, uint64_t cache_bytes, const mpk_options &opt) {
     if (p < 1 || p > MPK_MAX_POWER) return fail(MPK_ERR_ARG, "p must be in [1, 32]");
     if (cache_bytes == 0) return fail(MPK_ERR_ARG, "cache budget must be > 0");
     if (!(opt.safety_factor > 0.0)) return fail(MPK_ERR_ARG, "safety factor must be > 0");
@@ -939,7 +955,71 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
     if (opt.skew < 1 || opt.skew > MPK_MAX_SKEW) return fail(MPK_ERR_ARG, "skew must be in [1, 32]");
     if (opt.plan_on_device != 0 && opt.plan_on_device != 1) return fail(MPK_ERR_ARG, "plan_on_device must be 0 or 1");
     if (opt.force_acquire != 0 && opt.force_acquire != 1) return fail(MPK_ERR_ARG, "force_acquire must be 0 or 1");
-    if (opt.recursion_stages < 0 || opt.recursion_stages > 16) return fail(MPK_ERR_ARG, "recursion_stages must be in [0, 16]");
+    if (opt.recursion_stages < 0 || opt.recursion_stages > 16)
+        return fail(MPK_ERR_ARG, "recursion_stages must be in [0, 16]");
+    return MPK_OK;
+}
+
+// Nonzeros and widest level from the renumbered row pointers.
+void level_counts(HostPlan &hp) {
+    const int64_t L = (int64_t)hp.level_ptr.size() - 1;
+    hp.level_nnz.assign(L, 0);
+    hp.max_level_rows = 0;
+    for (int64_t l = 0; l < L; ++l) {
+        hp.level_nnz[l] = (int64_t)hp.rowptr[hp.level_ptr[l + 1]] - hp.rowptr[hp.level_ptr[l]];
+        hp.max_level_rows = std::max<int64_t>(hp.max_level_rows, hp.level_ptr[l + 1] - hp.level_ptr[l]);
+    }
+}
+
+}  // namespace
+
+mpk_status build_resident_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes, const mpk_options &opt,
+                               HostPlan &hp, ResidentMatrix *M) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!A) return fail(MPK_ERR_ARG, "null matrix");
+    if (A->n < 0) return fail(MPK_ERR_CSR, "negative n");
+    if (A->n > (int64_t)std::numeric_limits<int32_t>::max() - 1)
+        return fail(MPK_ERR_UNSUPPORTED, "n >= 2^31 is not supported");
+    if (A->nnz < 0) return fail(MPK_ERR_CSR, "negative nnz");
+    if (A->nnz > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(MPK_ERR_UNSUPPORTED, "nnz >= 2^31 is not supported");
+    if (!A->rowptr) return fail(MPK_ERR_ARG, "null rowptr");
+    if (A->nnz > 0 && (!A->col || !A->val)) return fail(MPK_ERR_ARG, "null col/val");
+    mpk_status st = check_create_options(p, cache_bytes, opt);
+    if (st != MPK_OK) return st;
+    if (opt.recursion_stages != 0)
+        return fail(MPK_ERR_UNSUPPORTED, "recursion (Sec. 4.4) refines on the host: plan from host memory");
+    hp.n = A->n;
+    hp.nnz = A->nnz;
+    hp.p = p;
+    hp.cache_bytes = cache_bytes;
+    hp.opt = opt;
+    hp.opt.plan_on_device = 1;
+    st = device_plan_resident(A, opt.root_mode, &hp.root, hp.perm, hp.level_ptr, hp.rowptr, M, hp.phase_seconds);
+    if (st != MPK_OK) return st;
+    hp.dev_rowptr = M->rowptr;
+    hp.dev_col = M->col;
+    try {
+        hp.iperm.assign(hp.n, 0);
+        for (int64_t i = 0; i < hp.n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
+        level_counts(hp);
+    } catch (const std::bad_alloc &) {
+        return fail(MPK_ERR_OOM, "host allocation failed while planning");
+    }
+    auto ts0 = std::chrono::steady_clock::now();
+    st = build_schedule(hp, p, cache_bytes, opt);
+    if (st != MPK_OK) return st;
+    hp.phase_seconds[3] = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
+    hp.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MPK_OK;
+}
+
+mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
+                           const mpk_options &opt, HostPlan &hp) {
+    auto t0 = std::chrono::steady_clock::now();
+    mpk_status st = validate_csr(A);
+    if (st != MPK_OK) return st;
+    if ((st = check_create_options(p, cache_bytes, opt)) != MPK_OK) return st;
 
     const int64_t n = A->n;
     hp.n = n;

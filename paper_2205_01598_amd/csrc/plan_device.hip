@@ -14,9 +14,12 @@
 //   scatter  after a scan of the workgroup totals, every frontier vertex
 //            writes the neighbours it owns, in adjacency order, at
 //            b + its offset.
-// The host reads back the new frontier's size (4 bytes) per level.  An empty
-// frontier with vertices left starts a new component at the smallest
-// unnumbered index (a reduction), as a new level.  owner[v] is INT32_MAX for
+// The frontier bounds live in device memory (Frontier), and a fourth
+// one-thread kernel records the level and moves the frontier on, so the host
+// enqueues levels in batches (1, 2, 4, ... up to 32) and reads the state back
+// once per batch; levels enqueued after the component is exhausted do
+// nothing.  An empty frontier with vertices left starts a new component at
+// the smallest unnumbered index (a reduction), as a new level.  owner[v] is INT32_MAX for
 // an unnumbered vertex and a position below the current frontier otherwise.
 //
 // The George-Liu pseudo-peripheral search runs component-restricted sweeps of
@@ -49,47 +52,61 @@ __global__ void set_root(int32_t *order, int32_t *owner, int64_t pos, const int3
     owner[r] = -1;
 }
 
+// Frontier of the level expansion: order[a, b); next = size of the next
+// frontier (set by scan_blocks); lv = levels recorded in the level-end array.
+struct Frontier {
+    int64_t a, b, next, lv;
+};
+
 __global__ void claim(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                      const int32_t *__restrict__ order, int64_t a, int64_t b, int32_t *owner) {
-    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    if (f >= b) return;
-    const int32_t u = order[f];
-    for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
-        int32_t *w = owner + adj[j];
-        if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)f)
-            atomicMin(w, (int32_t)f);
-    }
-}
-
-// per frontier vertex: owned-neighbour count; exclusive offset inside the
-// workgroup in local[]; workgroup total in blocksum[]
-__global__ void count(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                      const int32_t *__restrict__ order, const int32_t *__restrict__ owner, int64_t a, int64_t b,
-                      int32_t *__restrict__ local, int32_t *__restrict__ blocksum) {
-    __shared__ int32_t s[kThreads];
-    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    int32_t c = 0;
-    if (f < b) {
+                      const int32_t *__restrict__ order, const Frontier *__restrict__ fr, int32_t *owner) {
+    const int64_t a = fr->a, b = fr->b;
+    for (int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x; f < b; f += (int64_t)gridDim.x * kThreads) {
         const int32_t u = order[f];
-        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) c += owner[adj[j]] == (int32_t)f;
+        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
+            int32_t *w = owner + adj[j];
+            if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)f)
+                atomicMin(w, (int32_t)f);
+        }
     }
-    s[threadIdx.x] = c;
-    __syncthreads();
-    // inclusive Hillis-Steele scan over the workgroup
-    for (int d = 1; d < kThreads; d <<= 1) {
-        const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (f < b) local[f - a] = s[threadIdx.x] - c;
-    if (threadIdx.x == kThreads - 1) blocksum[blockIdx.x] = s[kThreads - 1];
 }
 
-// one workgroup: exclusive scan of nb workgroup totals in place, grand total
-// to *total
-__global__ void scan_blocks(int32_t *blocksum, int64_t nb, int32_t *total) {
+// per frontier vertex: owned-neighbour count; exclusive offset inside its
+// chunk of kThreads frontier positions in local[]; chunk totals in
+// blocksum[] (chunks spread over the workgroups)
+__global__ void count(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                      const int32_t *__restrict__ order, const int32_t *__restrict__ owner,
+                      const Frontier *__restrict__ fr, int32_t *__restrict__ local, int32_t *__restrict__ blocksum) {
     __shared__ int32_t s[kThreads];
+    const int64_t a = fr->a, b = fr->b;
+    const int64_t nb = (b - a + kThreads - 1) / kThreads;
+    for (int64_t c = blockIdx.x; c < nb; c += gridDim.x) {
+        const int64_t f = a + c * kThreads + threadIdx.x;
+        int32_t k = 0;
+        if (f < b) {
+            const int32_t u = order[f];
+            for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) k += owner[adj[j]] == (int32_t)f;
+        }
+        s[threadIdx.x] = k;
+        __syncthreads();
+        // inclusive Hillis-Steele scan over the chunk
+        for (int d = 1; d < kThreads; d <<= 1) {
+            const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (f < b) local[f - a] = s[threadIdx.x] - k;
+        if (threadIdx.x == kThreads - 1) blocksum[c] = s[kThreads - 1];
+        __syncthreads();
+    }
+}
+
+// one workgroup: exclusive scan of the chunk totals in place, grand total to
+// fr->next
+__global__ void scan_blocks(int32_t *blocksum, Frontier *fr) {
+    __shared__ int32_t s[kThreads];
+    const int64_t nb = (fr->b - fr->a + kThreads - 1) / kThreads;
     int32_t carry = 0;
     for (int64_t base = 0; base < nb; base += kThreads) {
         const int64_t i = base + threadIdx.x;
@@ -107,20 +124,33 @@ __global__ void scan_blocks(int32_t *blocksum, int64_t nb, int32_t *total) {
         __syncthreads();
         carry += step;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) fr->next = carry;
 }
 
 __global__ void scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                        int32_t *__restrict__ order, const int32_t *__restrict__ owner, int64_t a, int64_t b,
-                        const int32_t *__restrict__ local, const int32_t *__restrict__ blocksum) {
-    const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    if (f >= b) return;
-    const int32_t u = order[f];
-    int64_t o = b + blocksum[blockIdx.x] + local[f - a];
-    for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
-        const int32_t v = adj[j];
-        if (owner[v] == (int32_t)f) order[o++] = v;
+                        int32_t *__restrict__ order, const int32_t *__restrict__ owner,
+                        const Frontier *__restrict__ fr, const int32_t *__restrict__ local,
+                        const int32_t *__restrict__ blocksum) {
+    const int64_t a = fr->a, b = fr->b;
+    for (int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x; f < b; f += (int64_t)gridDim.x * kThreads) {
+        const int32_t u = order[f];
+        int64_t o = b + blocksum[(f - a) / kThreads] + local[f - a];
+        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
+            const int32_t v = adj[j];
+            if (owner[v] == (int32_t)f) order[o++] = v;
+        }
     }
+}
+
+// one thread: a non-empty frontier becomes a level (its end recorded) and
+// the next frontier follows it
+__global__ void advance(Frontier *fr, int32_t *level_end) {
+    const int64_t a = fr->a, b = fr->b;
+    if (a >= b) return;
+    level_end[fr->lv] = (int32_t)b;
+    fr->lv = fr->lv + 1;
+    fr->a = b;
+    fr->b = b + fr->next;
 }
 
 // smallest index v with owner[v] == INT32_MAX (n if none)
@@ -146,7 +176,8 @@ struct DeviceGraph {
     int64_t n = 0;
     int64_t *ptr = nullptr;
     int32_t *adj = nullptr, *owner = nullptr, *order = nullptr, *local = nullptr, *blocksum = nullptr,
-            *scalar = nullptr;
+            *scalar = nullptr, *level_end = nullptr;
+    Frontier *front = nullptr;
     unsigned long long *key = nullptr;
     std::vector<void *> allocs;
     ~DeviceGraph() {
@@ -175,25 +206,30 @@ inline unsigned grid_for(int64_t items) { return (unsigned)((items + kThreads - 
 // the component is exhausted; appends level ends to lptr.  Returns the
 // position after the component in *end.
 mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> &lptr, int64_t *end) {
-    int64_t a = start, b = start + 1;
-    while (a < b) {
-        const int64_t F = b - a;
-        const unsigned nb = grid_for(F);
-        hipLaunchKernelGGL(claim, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, a, b, g.owner);
-        hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, a, b, g.local,
-                           g.blocksum);
-        hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, (int64_t)nb, g.scalar);
-        hipLaunchKernelGGL(scatter, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, a, b, g.local,
-                           g.blocksum);
+    Frontier h{start, start + 1, 0, 0};
+    LV_TRY(hipMemcpy(g.front, &h, sizeof(h), hipMemcpyHostToDevice));
+    const unsigned nb = std::max(1u, std::min(grid_for(g.n), 1024u));
+    for (int batch = 1;; batch = std::min(2 * batch, 32)) {
+        for (int i = 0; i < batch; ++i) {
+            hipLaunchKernelGGL(claim, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.front, g.owner);
+            hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
+                               g.local, g.blocksum);
+            hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, g.front);
+            hipLaunchKernelGGL(scatter, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
+                               g.local, g.blocksum);
+            hipLaunchKernelGGL(advance, dim3(1), dim3(1), 0, 0, g.front, g.level_end);
+        }
         LV_TRY(hipGetLastError());
-        int32_t next = 0;
-        LV_TRY(hipMemcpy(&next, g.scalar, sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (next < 0 || b + next > g.n) return fail(MPK_ERR_HIP, "device levels: inconsistent frontier size");
-        lptr.push_back((int32_t)b);
-        a = b;
-        b += next;
+        LV_TRY(hipMemcpy(&h, g.front, sizeof(h), hipMemcpyDeviceToHost));
+        if (h.b > g.n || h.a > h.b || h.lv > g.n) return fail(MPK_ERR_HIP, "device levels: inconsistent frontier");
+        if (h.a == h.b) break;
     }
-    *end = a;
+    if (h.lv > 0) {
+        const size_t base = lptr.size();
+        lptr.resize(base + (size_t)h.lv);
+        LV_TRY(hipMemcpy(lptr.data() + base, g.level_end, sizeof(int32_t) * h.lv, hipMemcpyDeviceToHost));
+    }
+    *end = h.a;
     return MPK_OK;
 }
 
@@ -223,6 +259,8 @@ mpk_status alloc_bfs(DeviceGraph &g) {
     LV_TRY(dalloc(g, &g.blocksum, (n + kThreads - 1) / kThreads));
     LV_TRY(dalloc(g, &g.scalar, 1));
     LV_TRY(dalloc(g, &g.key, 1));
+    LV_TRY(dalloc(g, &g.level_end, n + 1));
+    LV_TRY(dalloc(g, &g.front, 1));
     return MPK_OK;
 }
 
@@ -591,6 +629,313 @@ mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, s
     phase_seconds[1] = secs(t1, t2);
     phase_seconds[2] = secs(t2, t3);
     *handled = true;
+    return MPK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plans from a CSR in device memory: the renumbered matrix stays on the GPU
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The checks of validate_csr, on the device: bit 1 = row pointers (not
+// monotone, outside [0, nnz], rowptr[0] != 0 or rowptr[n] != nnz), bit 2 = a
+// column outside [0, n).  A row's columns are read only when its bounds are
+// valid.
+__global__ void check_csr(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n, int64_t nnz,
+                          int32_t *bad) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(bad, 1);
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = rp[u], b = rp[u + 1];
+        if (a < 0 || a > b || b > nnz) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        for (int64_t j = a; j < b; ++j)
+            if ((uint32_t)col[j] >= (uint64_t)n) {
+                atomicOr(bad, 2);
+                break;
+            }
+    }
+}
+
+// longest row (atomic maximum of the row lengths)
+__global__ void max_row_length(const int64_t *__restrict__ rp, int64_t n, unsigned long long *out) {
+    unsigned long long m = 0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (unsigned long long)(rp[u + 1] - rp[u]));
+    atomicMax(out, m);
+}
+
+__global__ void narrow_rowptr(const int64_t *__restrict__ in, int64_t n1, int32_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n1; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)in[i];
+}
+
+// Rows longer than kSortOnDevice, one workgroup each: the keys (new column,
+// position in the row of A) are sorted in LDS by a bitonic network; the
+// positions make every key distinct, so the order is the stable order of
+// the host planner.  Values are taken from A at the original positions.
+constexpr int kLongRow = (int)kResidentRowMax;
+__global__ void __launch_bounds__(kThreads) sort_long_rows(const int32_t *__restrict__ rows,
+                                                           const int64_t *__restrict__ nrp,
+                                                           const int64_t *__restrict__ rp,
+                                                           const double *__restrict__ val,
+                                                           const int32_t *__restrict__ perm,
+                                                           int32_t *__restrict__ ncol, double *__restrict__ nval) {
+    __shared__ unsigned long long key[kLongRow];
+    const int32_t r = rows[blockIdx.x];
+    const int64_t a = nrp[r], len = nrp[r + 1] - a;  // len <= kLongRow (checked on the host)
+    const int64_t a0 = rp[perm[r]];
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kThreads)
+        key[i] = i < len ? ((unsigned long long)(uint32_t)ncol[a + i] << 32) | (uint32_t)i : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kThreads) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = key[i], y = key[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        key[i] = y;
+                        key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < len; i += kThreads) {
+        const unsigned long long kk = key[i];
+        ncol[a + i] = (int32_t)(kk >> 32);
+        nval[a + i] = val[a0 + (uint32_t)kk];
+    }
+}
+
+// One workgroup per tile (grid stride): per m, the minimum and maximum
+// column inside the row range of group g-1+m; bad flag for any other column.
+__global__ void __launch_bounds__(kThreads) tile_columns(const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ tile_row,
+                                                         const int32_t *__restrict__ tile_group,
+                                                         const int32_t *__restrict__ group_row, int64_t T,
+                                                         int64_t G, int32_t *__restrict__ out, int32_t *bad) {
+    __shared__ int32_t red[6][kThreads];
+    for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const int64_t g = tile_group[t];
+        int32_t gb[3], ge[3], lo[3], hi[3];
+        for (int m = 0; m < 3; ++m) {
+            const int64_t gm = g - 1 + m;
+            gb[m] = (gm >= 0 && gm < G) ? group_row[gm] : 0;
+            ge[m] = (gm >= 0 && gm < G) ? group_row[gm + 1] : 0;
+            lo[m] = INT32_MAX;
+            hi[m] = -1;
+        }
+        const int64_t j0 = rowptr[tile_row[t]], j1 = rowptr[tile_row[t + 1]];
+        bool outside = false;
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += kThreads) {
+            const int32_t c = col[j];
+            int m = -1;
+            for (int mm = 0; mm < 3; ++mm)
+                if (c >= gb[mm] && c < ge[mm]) m = mm;
+            if (m < 0) {
+                outside = true;
+                continue;
+            }
+            for (int mm = 0; mm < 3; ++mm)
+                if (mm == m) {
+                    lo[mm] = min(lo[mm], c);
+                    hi[mm] = max(hi[mm], c);
+                }
+        }
+        if (outside) atomicOr(bad, 1);
+        for (int m = 0; m < 3; ++m) {
+            red[2 * m][threadIdx.x] = lo[m];
+            red[2 * m + 1][threadIdx.x] = hi[m];
+        }
+        __syncthreads();
+        for (int d = kThreads / 2; d > 0; d >>= 1) {
+            if ((int)threadIdx.x < d)
+                for (int m = 0; m < 3; ++m) {
+                    red[2 * m][threadIdx.x] = min(red[2 * m][threadIdx.x], red[2 * m][threadIdx.x + d]);
+                    red[2 * m + 1][threadIdx.x] = max(red[2 * m + 1][threadIdx.x], red[2 * m + 1][threadIdx.x + d]);
+                }
+            __syncthreads();
+        }
+        if (threadIdx.x < 6) out[6 * t + threadIdx.x] = red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// Adjacency of a sorted symmetric pattern on the device (rows without the
+// diagonal and repeats) into g.ptr / g.adj.  *symmetric = false (nothing
+// built) for other patterns.
+mpk_status device_adjacency(DeviceGraph &g, const int64_t *drp, const int32_t *dcol, int32_t *flag, int64_t *cnt,
+                            bool *symmetric) {
+    const int64_t n = g.n;
+    const int32_t one = 1;
+    LV_TRY(hipMemcpy(flag, &one, sizeof(int32_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(rows_sorted, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
+    hipLaunchKernelGGL(pattern_symmetric, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
+    LV_TRY(hipGetLastError());
+    int32_t ok = 0;
+    LV_TRY(hipMemcpy(&ok, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *symmetric = ok != 0;
+    if (!ok) return MPK_OK;
+    LV_TRY(dalloc(g, &g.ptr, n + 1));
+    hipLaunchKernelGGL(adjacency_count, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, cnt);
+    LV_TRY(hipGetLastError());
+    mpk_status st = scan_on_device(g, cnt, n, g.ptr);
+    if (st != MPK_OK) return st;
+    int64_t m = 0;
+    LV_TRY(hipMemcpy(&m, g.ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    LV_TRY(dalloc(g, &g.adj, m));
+    hipLaunchKernelGGL(adjacency_write, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, g.ptr, g.adj);
+    LV_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+struct ResidentGuard {  // frees the output matrix unless released
+    ResidentMatrix *M;
+    bool keep = false;
+    ~ResidentGuard() {
+        if (keep) return;
+        (void)hipFree(M->rowptr);
+        (void)hipFree(M->col);
+        (void)hipFree(M->val);
+        *M = ResidentMatrix{};
+    }
+};
+
+}  // namespace
+
+mpk_status device_plan_resident(const mpk_csr *A, int32_t root_mode, int64_t *root_out,
+                                std::vector<int32_t> &perm, std::vector<int32_t> &level_ptr,
+                                std::vector<int32_t> &rowptr, ResidentMatrix *M, double *phase_seconds) {
+    const int64_t n = A->n, nnz = A->nnz;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+    const auto t0 = now();
+    *M = ResidentMatrix{};
+    ResidentGuard guard{M};
+    auto mall = [](auto **p, int64_t count) {
+        return hipMalloc((void **)p, sizeof(**p) * (size_t)std::max<int64_t>(count, 1));
+    };
+    LV_TRY(mall(&M->rowptr, n + 1));
+    LV_TRY(mall(&M->col, nnz));
+    LV_TRY(mall(&M->val, nnz));
+    perm.assign(n, 0);
+    level_ptr.assign(1, 0);
+    rowptr.assign(n + 1, 0);
+    *root_out = 0;
+    if (n == 0) {
+        const int32_t zero = 0;
+        LV_TRY(hipMemcpy(M->rowptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+        guard.keep = true;
+        return MPK_OK;
+    }
+    const int64_t *drp = A->rowptr;
+    const int32_t *dcol = A->col;
+    DeviceGraph g;
+    g.n = n;
+    int32_t *flag = nullptr;
+    int64_t *cnt = nullptr;
+    unsigned long long *mx = nullptr;
+    LV_TRY(dalloc(g, &flag, 1));
+    LV_TRY(dalloc(g, &cnt, n));
+    LV_TRY(dalloc(g, &mx, 1));
+    // ---- validation, the host planner's checks -----------------------------------------
+    const int32_t zero = 0;
+    const unsigned long long zero64 = 0;
+    LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+    LV_TRY(hipMemcpy(mx, &zero64, sizeof(zero64), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(check_csr, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, nnz, flag);
+    LV_TRY(hipGetLastError());
+    int32_t bad = 0;
+    LV_TRY(hipMemcpy(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (bad & 1) return fail(MPK_ERR_CSR, "device CSR: row pointers not monotone or not in [0, nnz]");
+    if (bad & 2) return fail(MPK_ERR_CSR, "device CSR: column index out of range");
+    hipLaunchKernelGGL(max_row_length, dim3(2048), dim3(kThreads), 0, 0, drp, n, mx);
+    LV_TRY(hipGetLastError());
+    unsigned long long longest = 0;
+    LV_TRY(hipMemcpy(&longest, mx, sizeof(longest), hipMemcpyDeviceToHost));
+    if ((int64_t)longest > kResidentRowMax)
+        return fail(MPK_ERR_UNSUPPORTED, "device CSR: a row holds more than 4096 entries; plan it from host memory");
+    // ---- graph ------------------------------------------------------------------------
+    bool symmetric = false;
+    mpk_status st = device_adjacency(g, drp, dcol, flag, cnt, &symmetric);
+    if (st != MPK_OK) return st;
+    if (!symmetric)
+        return fail(MPK_ERR_UNSUPPORTED,
+                    "device CSR: rows must be sorted and the pattern symmetric; plan other matrices from host memory");
+    LV_TRY(hipDeviceSynchronize());
+    const auto t1 = now();
+    // ---- levels ------------------------------------------------------------------------
+    if ((st = alloc_bfs(g)) != MPK_OK) return st;
+    if ((st = bfs_on_device(g, root_mode, root_out, level_ptr)) != MPK_OK) return st;
+    LV_TRY(hipDeviceSynchronize());
+    const auto t2 = now();
+    // ---- renumbered matrix P A P^T, left on the device -----------------------------------
+    int32_t *iperm = nullptr, *long_rows = nullptr;
+    int64_t *nrp = nullptr;
+    LV_TRY(dalloc(g, &iperm, n));
+    LV_TRY(dalloc(g, &nrp, n + 1));
+    LV_TRY(dalloc(g, &long_rows, n));
+    LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(inverse_perm, dim3(2048), dim3(kThreads), 0, 0, g.order, n, iperm);
+    hipLaunchKernelGGL(new_lengths, dim3(2048), dim3(kThreads), 0, 0, drp, g.order, n, cnt);
+    LV_TRY(hipGetLastError());
+    if ((st = scan_on_device(g, cnt, n, nrp)) != MPK_OK) return st;
+    hipLaunchKernelGGL(renumber_rows, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, A->val, g.order, iperm, nrp, n,
+                       M->col, M->val, long_rows, flag);
+    LV_TRY(hipGetLastError());
+    int32_t n_long = 0;
+    LV_TRY(hipMemcpy(&n_long, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (n_long > 0) {
+        hipLaunchKernelGGL(sort_long_rows, dim3((unsigned)n_long), dim3(kThreads), 0, 0, long_rows, nrp, drp,
+                           A->val, g.order, M->col, M->val);
+        LV_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(narrow_rowptr, dim3(2048), dim3(kThreads), 0, 0, nrp, n + 1, M->rowptr);
+    LV_TRY(hipGetLastError());
+    LV_TRY(hipMemcpy(perm.data(), g.order, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    LV_TRY(hipMemcpy(rowptr.data(), M->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    const auto t3 = now();
+    phase_seconds[0] = secs(t0, t1);
+    phase_seconds[1] = secs(t1, t2);
+    phase_seconds[2] = secs(t2, t3);
+    guard.keep = true;
+    return MPK_OK;
+}
+
+mpk_status device_tile_columns(const int32_t *d_rowptr, const int32_t *d_col, const std::vector<int32_t> &tile_row,
+                               const std::vector<int32_t> &tile_group, const std::vector<int32_t> &group_row,
+                               std::vector<int32_t> &out, bool *bad) {
+    const int64_t T = (int64_t)tile_group.size(), G = (int64_t)group_row.size() - 1;
+    out.assign(6 * (size_t)T, 0);
+    *bad = false;
+    if (T == 0) return MPK_OK;
+    DeviceGraph g;  // owner of the temporary buffers
+    int32_t *dtr = nullptr, *dtg = nullptr, *dgr = nullptr, *dout = nullptr, *flag = nullptr;
+    LV_TRY(dalloc(g, &dtr, T + 1));
+    LV_TRY(dalloc(g, &dtg, T));
+    LV_TRY(dalloc(g, &dgr, G + 1));
+    LV_TRY(dalloc(g, &dout, 6 * T));
+    LV_TRY(dalloc(g, &flag, 1));
+    LV_TRY(hipMemcpy(dtr, tile_row.data(), sizeof(int32_t) * (T + 1), hipMemcpyHostToDevice));
+    LV_TRY(hipMemcpy(dtg, tile_group.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice));
+    LV_TRY(hipMemcpy(dgr, group_row.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice));
+    const int32_t zero = 0;
+    LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+    const unsigned nb = (unsigned)std::min<int64_t>(T, 8192);
+    hipLaunchKernelGGL(tile_columns, dim3(nb), dim3(kThreads), 0, 0, d_rowptr, d_col, dtr, dtg, dgr, T, G, dout,
+                       flag);
+    LV_TRY(hipGetLastError());
+    int32_t f = 0;
+    LV_TRY(hipMemcpy(out.data(), dout, sizeof(int32_t) * 6 * T, hipMemcpyDeviceToHost));
+    LV_TRY(hipMemcpy(&f, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *bad = f != 0;
     return MPK_OK;
 }
 

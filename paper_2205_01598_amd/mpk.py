@@ -121,6 +121,47 @@ class Plan:
         if upload:
             self.upload()
 
+    @classmethod
+    def from_device(cls, rowptr, col, val, p: int, cache_bytes: int, *, upload: bool = True, **opts):
+        """``mpk_plan_create_device``: plan a CSR held in GPU tensors
+        (int64 rowptr[n+1], int32 col[nnz], float64 val[nnz]; rows sorted,
+        pattern symmetric, at most 4096 entries per row).  Levels, renumbering
+        and P A P^T run on the GPU and the renumbered matrix stays there."""
+        arrays = ((rowptr, "rowptr", "torch.int64"), (col, "col", "torch.int32"), (val, "val", "torch.float64"))
+        for t, name, dt in arrays:
+            if not hasattr(t, "data_ptr") or not hasattr(t, "is_cuda"):
+                raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+            if str(t.dtype) != dt:
+                raise ValueError(f"{name}: dtype must be {dt}, got {t.dtype}")
+            if not t.is_contiguous():
+                raise ValueError(f"{name}: must be contiguous")
+        for t, name, _ in arrays:
+            if not t.is_cuda:
+                raise ValueError(f"{name}: must be a GPU (cuda) tensor")
+        n = rowptr.numel() - 1
+        if n < 0:
+            raise ValueError("rowptr: needs n + 1 >= 1 entries")
+        if val.numel() != col.numel():
+            raise ValueError(f"val: expected {col.numel()} elements (one per column index), got {val.numel()}")
+        s = _lib.mpk_csr(int(n), int(col.numel()),
+                         ctypes.cast(int(rowptr.data_ptr()), ctypes.POINTER(ctypes.c_int64)),
+                         ctypes.cast(int(col.data_ptr()), ctypes.POINTER(ctypes.c_int32)),
+                         ctypes.cast(int(val.data_ptr()), ctypes.POINTER(ctypes.c_double)))
+        o = default_options(**opts)
+        h = ctypes.c_void_p()
+        self = cls.__new__(cls)
+        self._h = None
+        check(lib().mpk_plan_create_device(ctypes.byref(s), int(p), int(cache_bytes), ctypes.byref(o),
+                                           ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.nnz = int(col.numel())
+        self.p = int(p)
+        self.nrhs = int(o.nrhs)
+        if upload:
+            self.upload()
+        return self
+
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib._lib is not None:
             lib().mpk_plan_destroy(self._h)

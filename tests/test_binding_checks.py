@@ -82,3 +82,21 @@ def test_recurrence_lengths_checked(plan):
     ok_len = Recurrence(np.ones(2), coef=np.ones(4), complex_pairs=True, acc=_t((64, 2)))
     with pytest.raises(ValueError, match="GPU"):
         plan.run(_t((64, 2)), _t((2, 64, 2)), ok_len, powers=2)
+
+
+def test_from_device_checks_arguments():
+    rp = torch.zeros(5, dtype=torch.int64)
+    col = torch.zeros(4, dtype=torch.int32)
+    val = torch.zeros(4, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        Plan.from_device(rp, col, val, 2, 1 << 20)
+    with pytest.raises(ValueError, match="rowptr: dtype"):
+        Plan.from_device(rp.to(torch.int32), col, val, 2, 1 << 20)
+    with pytest.raises(ValueError, match="col: dtype"):
+        Plan.from_device(rp, col.to(torch.int64), val, 2, 1 << 20)
+    with pytest.raises(ValueError, match="val: dtype"):
+        Plan.from_device(rp, col, val.to(torch.float32), 2, 1 << 20)
+    with pytest.raises(ValueError, match="contiguous"):
+        Plan.from_device(rp, torch.zeros(8, dtype=torch.int32)[::2], val, 2, 1 << 20)
+    with pytest.raises(ValueError, match="torch tensor"):
+        Plan.from_device(np.zeros(5, np.int64), col, val, 2, 1 << 20)
