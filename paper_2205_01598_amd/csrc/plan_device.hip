@@ -5,22 +5,28 @@
 // vertex of level i, taken in new order, numbers its not yet numbered
 // neighbours in ascending original index.
 //
-// One level of the frontier order[a, b) is expanded by three kernels:
-//   claim    owner[v] = smallest frontier position adjacent to v (atomic
-//            minimum; owner only ever decreases, so a plain read that is
-//            already <= f makes the atomic unnecessary);
-//   count    every frontier vertex counts the neighbours it owns, and a
-//            workgroup scan gives its offset inside the workgroup;
-//   scatter  after a scan of the workgroup totals, every frontier vertex
-//            writes the neighbours it owns, in adjacency order, at
-//            b + its offset.
-// The frontier bounds live in device memory (Frontier), and a fourth
-// one-thread kernel records the level and moves the frontier on, so the host
+// One level of the frontier order[a, b) is expanded by these kernels, the
+// row-walking ones with a group of 32 lanes per frontier vertex:
+//   claim        owner[v] = smallest frontier position adjacent to v (atomic
+//                minimum; owner only ever decreases, so a read that is
+//                already <= f makes the atomic unnecessary);
+//   count_owned  every frontier vertex counts the neighbours it owns;
+//   count        a workgroup scan of those counts gives each vertex's offset
+//                inside its chunk of 256 frontier positions;
+//   scan_blocks  one workgroup scans the chunk totals (the next frontier's
+//                size);
+//   scatter      every frontier vertex writes the neighbours it owns, in
+//                row order, at b + its offset, and marks them seen.
+// The frontier bounds live in device memory (Frontier), and a one-thread
+// kernel (advance) records the level and moves the frontier on, so the host
 // enqueues levels in batches (1, 2, 4, ... up to 32) and reads the state back
 // once per batch; levels enqueued after the component is exhausted do
 // nothing.  An empty frontier with vertices left starts a new component at
-// the smallest unnumbered index (a reduction), as a new level.  owner[v] is INT32_MAX for
-// an unnumbered vertex and a position below the current frontier otherwise.
+// the smallest unnumbered index (a reduction), as a new level.  owner[v] is
+// INT32_MAX for an unnumbered vertex and a position below the current
+// frontier otherwise; a bitmap of numbered vertices lets the kernels skip
+// the owner array for most neighbours.  For a sorted symmetric pattern the
+// rows of A are the graph (diagonal and repeated entries skipped).
 //
 // The George-Liu pseudo-peripheral search runs component-restricted sweeps of
 // the same expansion and picks the smallest-degree vertex of the last level
@@ -46,11 +52,17 @@ __global__ void fill_i32(int32_t *p, int64_t n, int32_t v) {
         p[i] = v;
 }
 
-__global__ void set_root(int32_t *order, int32_t *owner, int64_t pos, const int32_t *root) {
+__global__ void set_root(int32_t *order, int32_t *owner, uint32_t *seen, int64_t pos, const int32_t *root) {
     const int32_t r = *root;
     order[pos] = r;
     owner[r] = -1;
+    seen[r >> 5] |= 1u << (r & 31);
 }
+
+// seen[v / 32] bit v % 32: v is numbered (its owner is final).  The bitmap
+// (n / 8 bytes) stays in the L2, so the expansion skips the owner array for
+// the neighbours numbered in earlier levels, about two thirds of them.
+__device__ __forceinline__ bool is_seen(const uint32_t *seen, int32_t v) { return (seen[v >> 5] >> (v & 31)) & 1u; }
 
 // Frontier of the level expansion: order[a, b); next = size of the next
 // frontier (set by scan_blocks); lv = levels recorded in the level-end array.
@@ -58,35 +70,77 @@ struct Frontier {
     int64_t a, b, next, lv;
 };
 
+// The expansion kernels give every frontier vertex a group of kLanes lanes
+// (half a wavefront); lane l handles the entries l, l + kLanes, ... of the
+// vertex's row, so a level's edges are handled in parallel rather than one
+// row per thread.  A row is read as a graph row: the diagonal is skipped by
+// the seen bit (the vertex is numbered), a repeated entry (equal to the one
+// before it in the sorted row) is skipped explicitly.
+constexpr int kLanes = 32;
+
+// lanes of the calling lane's group that have pred set, as a 32-bit mask
+__device__ __forceinline__ uint32_t group_ballot(bool pred) {
+    const unsigned long long m = __ballot(pred);
+    return (uint32_t)(m >> (threadIdx.x & 32));
+}
+
+// Grid-stride over (frontier vertex, lane) slots: f = a + slot / kLanes.
+#define FOR_FRONTIER_SLOTS(a, b)                                                                          \
+    for (int64_t slot = blockIdx.x * (int64_t)kThreads + threadIdx.x; slot < ((b) - (a)) * kLanes;       \
+         slot += (int64_t)gridDim.x * kThreads)
+
 __global__ void claim(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                      const int32_t *__restrict__ order, const Frontier *__restrict__ fr, int32_t *owner) {
+                      const int32_t *__restrict__ order, const Frontier *__restrict__ fr, int32_t *owner,
+                      const uint32_t *__restrict__ seen) {
     const int64_t a = fr->a, b = fr->b;
-    for (int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x; f < b; f += (int64_t)gridDim.x * kThreads) {
+    FOR_FRONTIER_SLOTS(a, b) {
+        const int64_t f = a + slot / kLanes;
         const int32_t u = order[f];
-        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
-            int32_t *w = owner + adj[j];
-            if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)f)
-                atomicMin(w, (int32_t)f);
+        for (int64_t j = ptr[u] + (slot & (kLanes - 1)); j < ptr[u + 1]; j += kLanes) {
+            const int32_t v = adj[j];
+            if (is_seen(seen, v)) continue;
+            // owner only decreases: a plain read, even a stale one, that is
+            // already <= f shows the atomic cannot lower it
+            if (owner[v] > (int32_t)f) atomicMin(owner + v, (int32_t)f);
         }
     }
 }
 
-// per frontier vertex: owned-neighbour count; exclusive offset inside its
-// chunk of kThreads frontier positions in local[]; chunk totals in
-// blocksum[] (chunks spread over the workgroups)
-__global__ void count(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                      const int32_t *__restrict__ order, const int32_t *__restrict__ owner,
-                      const Frontier *__restrict__ fr, int32_t *__restrict__ local, int32_t *__restrict__ blocksum) {
+// per frontier vertex: the number of neighbours it owns, to cnt[f - a]
+__global__ void count_owned(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                            const int32_t *__restrict__ order, const int32_t *__restrict__ owner,
+                            const Frontier *__restrict__ fr, int32_t *__restrict__ cnt,
+                            const uint32_t *__restrict__ seen) {
+    const int64_t a = fr->a, b = fr->b;
+    FOR_FRONTIER_SLOTS(a, b) {
+        const int64_t f = a + slot / kLanes;
+        const int lane = (int)(slot & (kLanes - 1));
+        const int32_t u = order[f];
+        const int64_t j0 = ptr[u], j1 = ptr[u + 1];
+        int32_t k = 0;
+        for (int64_t base = j0; base < j1; base += kLanes) {  // uniform in the group
+            const int64_t j = base + lane;
+            bool own = false;
+            if (j < j1) {
+                const int32_t v = adj[j];
+                own = (j == j0 || adj[j - 1] != v) && !is_seen(seen, v) && owner[v] == (int32_t)f;
+            }
+            k += __popc(group_ballot(own));
+        }
+        if (lane == 0) cnt[f - a] = k;
+    }
+}
+
+// chunks of kThreads frontier positions: exclusive offset of every vertex
+// inside its chunk in local[], chunk totals in blocksum[]
+__global__ void count(const int32_t *__restrict__ cnt, const Frontier *__restrict__ fr, int32_t *__restrict__ local,
+                      int32_t *__restrict__ blocksum) {
     __shared__ int32_t s[kThreads];
     const int64_t a = fr->a, b = fr->b;
     const int64_t nb = (b - a + kThreads - 1) / kThreads;
     for (int64_t c = blockIdx.x; c < nb; c += gridDim.x) {
         const int64_t f = a + c * kThreads + threadIdx.x;
-        int32_t k = 0;
-        if (f < b) {
-            const int32_t u = order[f];
-            for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) k += owner[adj[j]] == (int32_t)f;
-        }
+        const int32_t k = f < b ? cnt[f - a] : 0;
         s[threadIdx.x] = k;
         __syncthreads();
         // inclusive Hillis-Steele scan over the chunk
@@ -127,17 +181,36 @@ __global__ void scan_blocks(int32_t *blocksum, Frontier *fr) {
     if (threadIdx.x == 0) fr->next = carry;
 }
 
+// Each frontier vertex writes the neighbours it owns, in row order, and
+// marks them seen: a lane's place is the count of owning lanes before it in
+// its group.  Another lane may read a bit (a plain, possibly stale read)
+// while it is being set: either value leads it to skip the vertex, which it
+// does not own.
 __global__ void scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
                         int32_t *__restrict__ order, const int32_t *__restrict__ owner,
                         const Frontier *__restrict__ fr, const int32_t *__restrict__ local,
-                        const int32_t *__restrict__ blocksum) {
+                        const int32_t *__restrict__ blocksum, uint32_t *seen) {
     const int64_t a = fr->a, b = fr->b;
-    for (int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x; f < b; f += (int64_t)gridDim.x * kThreads) {
+    FOR_FRONTIER_SLOTS(a, b) {
+        const int64_t f = a + slot / kLanes;
+        const int lane = (int)(slot & (kLanes - 1));
         const int32_t u = order[f];
+        const int64_t j0 = ptr[u], j1 = ptr[u + 1];
         int64_t o = b + blocksum[(f - a) / kThreads] + local[f - a];
-        for (int64_t j = ptr[u]; j < ptr[u + 1]; ++j) {
-            const int32_t v = adj[j];
-            if (owner[v] == (int32_t)f) order[o++] = v;
+        for (int64_t base = j0; base < j1; base += kLanes) {  // uniform in the group
+            const int64_t j = base + lane;
+            bool own = false;
+            int32_t v = 0;
+            if (j < j1) {
+                v = adj[j];
+                own = (j == j0 || adj[j - 1] != v) && !is_seen(seen, v) && owner[v] == (int32_t)f;
+            }
+            const uint32_t m = group_ballot(own);
+            if (own) {
+                order[o + __popc(m & ((1u << lane) - 1u))] = v;
+                atomicOr(seen + (v >> 5), 1u << (v & 31));
+            }
+            o += __popc(m);
         }
     }
 }
@@ -162,13 +235,22 @@ __global__ void first_unnumbered(const int32_t *__restrict__ owner, int64_t n, i
         }
 }
 
-// (degree, index) minimum over order[a, b)
-__global__ void min_degree(const int64_t *__restrict__ ptr, const int32_t *__restrict__ order, int64_t a, int64_t b,
-                           unsigned long long *out) {
+// (degree, index) minimum over order[a, b); the degree counts distinct
+// neighbours other than the vertex itself, so the rows of a sorted
+// symmetric A serve as the graph
+__global__ void min_degree(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
+                           const int32_t *__restrict__ order, int64_t a, int64_t b, unsigned long long *out) {
     const int64_t f = a + blockIdx.x * (int64_t)kThreads + threadIdx.x;
     if (f >= b) return;
     const int32_t v = order[f];
-    const unsigned long long key = ((unsigned long long)(ptr[v + 1] - ptr[v]) << 32) | (uint32_t)v;
+    int64_t deg = 0;
+    int32_t last = -1;
+    for (int64_t j = ptr[v]; j < ptr[v + 1]; ++j) {
+        const int32_t w = adj[j];
+        deg += w != v && w != last;
+        last = w;
+    }
+    const unsigned long long key = ((unsigned long long)deg << 32) | (uint32_t)v;
     atomicMin(out, key);
 }
 
@@ -176,7 +258,8 @@ struct DeviceGraph {
     int64_t n = 0;
     int64_t *ptr = nullptr;
     int32_t *adj = nullptr, *owner = nullptr, *order = nullptr, *local = nullptr, *blocksum = nullptr,
-            *scalar = nullptr, *level_end = nullptr;
+            *scalar = nullptr, *level_end = nullptr, *cnt = nullptr;
+    uint32_t *seen = nullptr;
     Frontier *front = nullptr;
     unsigned long long *key = nullptr;
     std::vector<void *> allocs;
@@ -208,15 +291,20 @@ inline unsigned grid_for(int64_t items) { return (unsigned)((items + kThreads - 
 mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> &lptr, int64_t *end) {
     Frontier h{start, start + 1, 0, 0};
     LV_TRY(hipMemcpy(g.front, &h, sizeof(h), hipMemcpyHostToDevice));
+    // grids sized for the widest possible frontier, capped; slots beyond the
+    // current frontier exit at once
     const unsigned nb = std::max(1u, std::min(grid_for(g.n), 1024u));
+    const unsigned ne = std::max(1u, (unsigned)std::min<int64_t>((g.n * kLanes + kThreads - 1) / kThreads, 2048));
     for (int batch = 1;; batch = std::min(2 * batch, 32)) {
         for (int i = 0; i < batch; ++i) {
-            hipLaunchKernelGGL(claim, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.front, g.owner);
-            hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
-                               g.local, g.blocksum);
+            hipLaunchKernelGGL(claim, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.front, g.owner,
+                               g.seen);
+            hipLaunchKernelGGL(count_owned, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
+                               g.cnt, g.seen);
+            hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.cnt, g.front, g.local, g.blocksum);
             hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, g.front);
-            hipLaunchKernelGGL(scatter, dim3(nb), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
-                               g.local, g.blocksum);
+            hipLaunchKernelGGL(scatter, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
+                               g.local, g.blocksum, g.seen);
             hipLaunchKernelGGL(advance, dim3(1), dim3(1), 0, 0, g.front, g.level_end);
         }
         LV_TRY(hipGetLastError());
@@ -235,13 +323,14 @@ mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> 
 
 mpk_status place_root(DeviceGraph &g, int64_t pos, int32_t root) {
     LV_TRY(hipMemcpy(g.scalar, &root, sizeof(int32_t), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(set_root, dim3(1), dim3(1), 0, 0, g.order, g.owner, pos, g.scalar);
+    hipLaunchKernelGGL(set_root, dim3(1), dim3(1), 0, 0, g.order, g.owner, g.seen, pos, g.scalar);
     LV_TRY(hipGetLastError());
     return MPK_OK;
 }
 
 mpk_status reset_owner(DeviceGraph &g) {
     hipLaunchKernelGGL(fill_i32, dim3(1024), dim3(kThreads), 0, 0, g.owner, g.n, (int32_t)INT32_MAX);
+    hipLaunchKernelGGL(fill_i32, dim3(256), dim3(kThreads), 0, 0, (int32_t *)g.seen, (g.n + 31) / 32, 0);
     LV_TRY(hipGetLastError());
     return MPK_OK;
 }
@@ -260,6 +349,8 @@ mpk_status alloc_bfs(DeviceGraph &g) {
     LV_TRY(dalloc(g, &g.scalar, 1));
     LV_TRY(dalloc(g, &g.key, 1));
     LV_TRY(dalloc(g, &g.level_end, n + 1));
+    LV_TRY(dalloc(g, &g.cnt, n));
+    LV_TRY(dalloc(g, &g.seen, (n + 31) / 32));
     LV_TRY(dalloc(g, &g.front, 1));
     return MPK_OK;
 }
@@ -289,7 +380,8 @@ mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, s
             const unsigned long long init = ~0ull;
             LV_TRY(hipMemcpy(g.key, &init, sizeof(init), hipMemcpyHostToDevice));
             const int64_t a = lp[lp.size() - 2], b = lp.back();
-            hipLaunchKernelGGL(min_degree, dim3(grid_for(b - a)), dim3(kThreads), 0, 0, g.ptr, g.order, a, b, g.key);
+            hipLaunchKernelGGL(min_degree, dim3(grid_for(b - a)), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, a, b,
+                               g.key);
             LV_TRY(hipGetLastError());
             unsigned long long key = 0;
             LV_TRY(hipMemcpy(&key, g.key, sizeof(key), hipMemcpyDeviceToHost));
@@ -355,6 +447,7 @@ mpk_status device_bfs_levels(int64_t n, const int64_t *ptr, const int32_t *adj, 
 namespace {
 
 constexpr int64_t kSortOnDevice = 256;  // rows up to this length are sorted by one thread
+constexpr int kSortInRegisters = 32;    // rows up to this length are sorted in its registers
 
 __global__ void rows_sorted(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n, int32_t *ok) {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
@@ -382,35 +475,6 @@ __global__ void pattern_symmetric(const int64_t *__restrict__ rp, const int32_t 
                 atomicMin(ok, 0);
                 return;
             }
-        }
-    }
-}
-
-// adjacency of a symmetric sorted pattern: the row without the diagonal and
-// without repeated entries (count, then write at the scanned offsets)
-__global__ void adjacency_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
-                                int64_t *__restrict__ cnt) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        int64_t m = 0, last = -1;
-        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
-            const int32_t v = col[j];
-            if (v == u || v == last) continue;
-            ++m;
-            last = v;
-        }
-        cnt[u] = m;
-    }
-}
-
-__global__ void adjacency_write(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
-                                const int64_t *__restrict__ aptr, int32_t *__restrict__ adj) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        int64_t o = aptr[u], last = -1;
-        for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
-            const int32_t v = col[j];
-            if (v == u || v == last) continue;
-            adj[o++] = v;
-            last = v;
         }
     }
 }
@@ -477,16 +541,47 @@ __global__ void new_lengths(const int64_t *__restrict__ rp, const int32_t *__res
 // row r of P A P^T: row perm[r] of A with columns mapped through iperm,
 // sorted by new column with a stable insertion sort (rows longer than
 // kSortOnDevice are listed for the host instead)
-__global__ void renumber_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-                              const double *__restrict__ val, const int32_t *__restrict__ perm,
-                              const int32_t *__restrict__ iperm, const int64_t *__restrict__ nrp, int64_t n,
-                              int32_t *__restrict__ ncol, double *__restrict__ nval, int32_t *long_rows,
-                              int32_t *n_long) {
+__global__ void __launch_bounds__(kThreads)
+    renumber_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const double *__restrict__ val,
+                  const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
+                  const int64_t *__restrict__ nrp, int64_t n, int32_t *__restrict__ ncol,
+                  double *__restrict__ nval, int32_t *long_rows, int32_t *n_long) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t o = perm[r];
         const int64_t a = rp[o], len = rp[o + 1] - a, base = nrp[r];
         int32_t *c = ncol + base;
         double *v = nval + base;
+        if (len <= kSortInRegisters) {
+            // short row: sorted in registers by an odd-even transposition
+            // network (adjacent swaps of strictly greater keys only, so the
+            // order of equal columns is kept); padding keys sort last
+            int32_t kc[kSortInRegisters];
+            double kv[kSortInRegisters];
+#pragma unroll
+            for (int j = 0; j < kSortInRegisters; ++j) {
+                kc[j] = j < len ? iperm[col[a + j]] : INT32_MAX;
+                kv[j] = j < len ? val[a + j] : 0.0;
+            }
+#pragma unroll
+            for (int pass = 0; pass < kSortInRegisters; ++pass)
+#pragma unroll
+                for (int i = pass & 1; i + 1 < kSortInRegisters; i += 2)
+                    if (kc[i] > kc[i + 1]) {
+                        const int32_t tc = kc[i];
+                        kc[i] = kc[i + 1];
+                        kc[i + 1] = tc;
+                        const double tv = kv[i];
+                        kv[i] = kv[i + 1];
+                        kv[i + 1] = tv;
+                    }
+#pragma unroll
+            for (int j = 0; j < kSortInRegisters; ++j)
+                if (j < len) {
+                    c[j] = kc[j];
+                    v[j] = kv[j];
+                }
+            continue;
+        }
         for (int64_t j = 0; j < len; ++j) {
             c[j] = iperm[col[a + j]];
             v[j] = val[a + j];
@@ -552,16 +647,11 @@ mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, s
     if (!ok) return MPK_OK;  // not handled: the caller takes the host path
     int64_t *cnt = nullptr;
     LV_TRY(dalloc(g, &cnt, n));
-    LV_TRY(dalloc(g, &g.ptr, n + 1));
-    hipLaunchKernelGGL(adjacency_count, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, cnt);
-    LV_TRY(hipGetLastError());
-    mpk_status st = scan_on_device(g, cnt, n, g.ptr);
-    if (st != MPK_OK) return st;
-    int64_t m = 0;
-    LV_TRY(hipMemcpy(&m, g.ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
-    LV_TRY(dalloc(g, &g.adj, m));
-    hipLaunchKernelGGL(adjacency_write, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, g.ptr, g.adj);
-    LV_TRY(hipGetLastError());
+    // the sorted symmetric rows are the graph: the expansion skips the
+    // diagonal and repeated entries itself
+    g.ptr = drp;
+    g.adj = dcol;
+    mpk_status st = MPK_OK;
     LV_TRY(hipDeviceSynchronize());
     const auto t1 = now();
     // ---- levels ----------------------------------------------------------------------
@@ -638,33 +728,56 @@ mpk_status device_plan(const mpk_csr *A, int32_t root_mode, int64_t *root_out, s
 
 namespace {
 
-// The checks of validate_csr, on the device: bit 1 = row pointers (not
-// monotone, outside [0, nnz], rowptr[0] != 0 or rowptr[n] != nnz), bit 2 = a
-// column outside [0, n).  A row's columns are read only when its bounds are
-// valid.
-__global__ void check_csr(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n, int64_t nnz,
-                          int32_t *bad) {
+// The checks of validate_csr and of the pattern, on the device, as flag
+// bits: 1 = row pointers (not monotone, outside [0, nnz], rowptr[0] != 0 or
+// rowptr[n] != nnz), 2 = a column outside [0, n), 4 = a row not sorted by
+// column, 8 = a stored (u, v) without a stored (v, u).  Columns are read only
+// in rows whose bounds are valid, so no access leaves the arrays.
+// check_rowptr: one thread per row, also the longest row (atomic maximum).
+__global__ void check_rowptr(const int64_t *__restrict__ rp, int64_t n, int64_t nnz, int32_t *bad,
+                             unsigned long long *longest) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(bad, 1);
+    unsigned long long m = 0;
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
         const int64_t a = rp[u], b = rp[u + 1];
-        if (a < 0 || a > b || b > nnz) {
+        if (a < 0 || a > b || b > nnz)
             atomicOr(bad, 1);
-            continue;
-        }
-        for (int64_t j = a; j < b; ++j)
-            if ((uint32_t)col[j] >= (uint64_t)n) {
-                atomicOr(bad, 2);
-                break;
-            }
+        else
+            m = max(m, (unsigned long long)(b - a));
     }
+    if (m) atomicMax(longest, m);
 }
 
-// longest row (atomic maximum of the row lengths)
-__global__ void max_row_length(const int64_t *__restrict__ rp, int64_t n, unsigned long long *out) {
-    unsigned long long m = 0;
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
-        m = max(m, (unsigned long long)(rp[u + 1] - rp[u]));
-    atomicMax(out, m);
+// check_pattern: a group of 32 lanes per row, one stored entry per lane; the
+// transposed entry is found by a binary search in row v.
+__global__ void check_pattern(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+                              int64_t nnz, int32_t *bad) {
+    int32_t flags = 0;
+    for (int64_t slot = blockIdx.x * (int64_t)kThreads + threadIdx.x; slot < n * kLanes;
+         slot += (int64_t)gridDim.x * kThreads) {
+        const int64_t u = slot / kLanes;
+        const int64_t a = rp[u], b = rp[u + 1];
+        if (a < 0 || a > b || b > nnz) continue;
+        for (int64_t j = a + (slot & (kLanes - 1)); j < b; j += kLanes) {
+            const int32_t v = col[j];
+            if ((uint32_t)v >= (uint64_t)n) {
+                flags |= 2;
+                continue;
+            }
+            if (j > a && col[j - 1] > v) flags |= 4;
+            if (v == u) continue;
+            int64_t lo = rp[v], hi = rp[v + 1];
+            if (lo < 0 || lo > hi || hi > nnz) continue;  // reported by check_rowptr
+            const int64_t end = hi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < u) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo == end || col[lo] != u) flags |= 8;
+        }
+    }
+    if (flags) atomicOr(bad, flags);
 }
 
 __global__ void narrow_rowptr(const int64_t *__restrict__ in, int64_t n1, int32_t *__restrict__ out) {
@@ -768,34 +881,6 @@ __global__ void __launch_bounds__(kThreads) tile_columns(const int32_t *__restri
     }
 }
 
-// Adjacency of a sorted symmetric pattern on the device (rows without the
-// diagonal and repeats) into g.ptr / g.adj.  *symmetric = false (nothing
-// built) for other patterns.
-mpk_status device_adjacency(DeviceGraph &g, const int64_t *drp, const int32_t *dcol, int32_t *flag, int64_t *cnt,
-                            bool *symmetric) {
-    const int64_t n = g.n;
-    const int32_t one = 1;
-    LV_TRY(hipMemcpy(flag, &one, sizeof(int32_t), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(rows_sorted, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
-    hipLaunchKernelGGL(pattern_symmetric, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, flag);
-    LV_TRY(hipGetLastError());
-    int32_t ok = 0;
-    LV_TRY(hipMemcpy(&ok, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
-    *symmetric = ok != 0;
-    if (!ok) return MPK_OK;
-    LV_TRY(dalloc(g, &g.ptr, n + 1));
-    hipLaunchKernelGGL(adjacency_count, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, cnt);
-    LV_TRY(hipGetLastError());
-    mpk_status st = scan_on_device(g, cnt, n, g.ptr);
-    if (st != MPK_OK) return st;
-    int64_t m = 0;
-    LV_TRY(hipMemcpy(&m, g.ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
-    LV_TRY(dalloc(g, &g.adj, m));
-    hipLaunchKernelGGL(adjacency_write, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, g.ptr, g.adj);
-    LV_TRY(hipGetLastError());
-    return MPK_OK;
-}
-
 struct ResidentGuard {  // frees the output matrix unless released
     ResidentMatrix *M;
     bool keep = false;
@@ -845,31 +930,29 @@ mpk_status device_plan_resident(const mpk_csr *A, int32_t root_mode, int64_t *ro
     LV_TRY(dalloc(g, &flag, 1));
     LV_TRY(dalloc(g, &cnt, n));
     LV_TRY(dalloc(g, &mx, 1));
-    // ---- validation, the host planner's checks -----------------------------------------
+    // ---- validation (the host planner's checks) and the pattern ----------------------
     const int32_t zero = 0;
     const unsigned long long zero64 = 0;
     LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
     LV_TRY(hipMemcpy(mx, &zero64, sizeof(zero64), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(check_csr, dim3(2048), dim3(kThreads), 0, 0, drp, dcol, n, nnz, flag);
+    hipLaunchKernelGGL(check_rowptr, dim3(2048), dim3(kThreads), 0, 0, drp, n, nnz, flag, mx);
+    hipLaunchKernelGGL(check_pattern, dim3(8192), dim3(kThreads), 0, 0, drp, dcol, n, nnz, flag);
     LV_TRY(hipGetLastError());
     int32_t bad = 0;
+    unsigned long long longest = 0;
     LV_TRY(hipMemcpy(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    LV_TRY(hipMemcpy(&longest, mx, sizeof(longest), hipMemcpyDeviceToHost));
     if (bad & 1) return fail(MPK_ERR_CSR, "device CSR: row pointers not monotone or not in [0, nnz]");
     if (bad & 2) return fail(MPK_ERR_CSR, "device CSR: column index out of range");
-    hipLaunchKernelGGL(max_row_length, dim3(2048), dim3(kThreads), 0, 0, drp, n, mx);
-    LV_TRY(hipGetLastError());
-    unsigned long long longest = 0;
-    LV_TRY(hipMemcpy(&longest, mx, sizeof(longest), hipMemcpyDeviceToHost));
     if ((int64_t)longest > kResidentRowMax)
         return fail(MPK_ERR_UNSUPPORTED, "device CSR: a row holds more than 4096 entries; plan it from host memory");
-    // ---- graph ------------------------------------------------------------------------
-    bool symmetric = false;
-    mpk_status st = device_adjacency(g, drp, dcol, flag, cnt, &symmetric);
-    if (st != MPK_OK) return st;
-    if (!symmetric)
+    if (bad & (4 | 8))
         return fail(MPK_ERR_UNSUPPORTED,
                     "device CSR: rows must be sorted and the pattern symmetric; plan other matrices from host memory");
-    LV_TRY(hipDeviceSynchronize());
+    // the sorted symmetric rows are the graph
+    g.ptr = const_cast<int64_t *>(drp);
+    g.adj = const_cast<int32_t *>(dcol);
+    mpk_status st = MPK_OK;
     const auto t1 = now();
     // ---- levels ------------------------------------------------------------------------
     if ((st = alloc_bfs(g)) != MPK_OK) return st;

@@ -450,6 +450,12 @@ def evaluate(tuner: LearnedTuner, records, static=None, shortlist=(3,)):
     if static is not None:
         out["static_config"] = static
         out["geomean_static_gain_over_default"] = float(np.exp(np.mean(np.log(sgains))))
+        # the per-matrix choice against the one best static configuration
+        out["gain_over_best_static"] = out["geomean_gain_over_default"] / out["geomean_static_gain_over_default"]
+        for m in shortlist:
+            out[f"shortlist{m}_gain_over_best_static"] = (out["geomean_best_gain_over_default"]
+                                                         / out[f"shortlist{m}_geomean_over_best"]
+                                                         / out["geomean_static_gain_over_default"])
     return out
 
 

@@ -50,18 +50,21 @@ def test_learned_tuner_beats_default_on_held_out():
     assert math.isfinite(loss)
     static = tune.best_static(train)
     m = tune.evaluate(tuner, test, static)
-    # the untuned default (C = 256 MB, skew 1, grid = all resident
-    # workgroups) is measurably worse than the choice of the trained network
-    # (on this database the sweep's best is 1.20x the default, geomean)
-    assert m["geomean_gain_over_default"] > 1.05, m
-    # the features matter: the per-matrix choice beats the one configuration
-    # that is best on the training matrices as a whole
-    assert m["geomean_gain_over_default"] > 1.02 * m["geomean_static_gain_over_default"], m
+    # The yardstick is the one configuration that is best on the training
+    # matrices as a whole (C = 128 MB, skew 4 on this database): the
+    # per-matrix choice has to beat it, so the features matter.  Measured on
+    # this database (N up to 1e7): 1.040-1.054x for training seeds 0-2 (the
+    # model's own pick) and 1.066x for the best of its three top-ranked
+    # configurations; the sweep's best is 1.20x the untuned default
+    # (C = 256 MB, skew 1, all resident workgroups), the static one 1.10x.
+    assert m["gain_over_best_static"] > 1.035, m
+    assert m["shortlist3_gain_over_best_static"] > 1.05, m
+    assert m["geomean_gain_over_default"] > 1.10, m
     # and the choice is close to the exhaustive sweep's best
-    assert m["geomean_pick_over_best"] < 1.08, m
+    assert m["geomean_pick_over_best"] < 1.06, m
     # measuring the model's three best configurations comes closer still
     assert m["shortlist3_geomean_over_best"] <= m["geomean_pick_over_best"], m
-    assert m["shortlist3_geomean_over_best"] < 1.05, m
+    assert m["shortlist3_geomean_over_best"] < 1.04, m
 
 
 class _RankNet:
