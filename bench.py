@@ -187,6 +187,29 @@ def vendor_spmv(torch, plan, X, Y, own_ms):
             "own_speedup": round(ms / own_ms, 3), "max_rel_diff_vs_own": fmt(diff)}
 
 
+def only_config(args):
+    """The headline matrix in one plan configuration, `steps` timed runs after
+    `warmup` (rocprofv3 runs of a single configuration)."""
+    import torch
+
+    import workloads as W
+    from paper_2205_01598_amd import Plan
+
+    sm, cmb, skew, tile, streams = (int(v) for v in args.only_config.split(","))
+    A, _ = W.stencil_27pt_random(args.n, seed=args.seed)
+    x = W.uniform_vector(A.n, seed=args.seed)
+    pl = Plan(A, args.p, cmb << 20, root_mode=1, skew=skew, tile_nnz=tile, xcd_streams=streams,
+              recursion_stages=sm)
+    perm = pl.arrays()[0].astype(np.int64)
+    X = torch.from_numpy(np.ascontiguousarray(x[perm])).cuda()
+    Y = torch.empty((args.p, A.n), dtype=torch.float64, device="cuda")
+    ms = timed(torch, lambda: pl.run(X, Y), args.steps, args.warmup)
+    pl.status()
+    inf = pl.info()
+    print(json.dumps({"config": args.only_config, "ms": round(ms, 4), "units": inf["n_units"],
+                      "tiles": inf["n_tiles"]}), flush=True)
+
+
 def bench_chebyshev(torch, Plan, W, dev, steps_err=10):
     """Anderson 128^3, degree-32 Chebyshev step as 4 MPK blocks of p = 8.
     Every configuration the autotuner picks is checked in the same run: one
@@ -511,7 +534,13 @@ def main():
                     help="load-only bandwidth versus footprint (one full pass per launch) and exit")
     ap.add_argument("--thin-levels-only", action="store_true",
                     help="only the thin-level 2D 9-point 4096^2 workload (for profiling); prints its JSON and exits")
+    ap.add_argument("--only-config", default=None, metavar="S_M,C_MB,SKEW,TILE,STREAMS",
+                    help="only the headline matrix in this plan configuration (recursion stages, budget in MB, "
+                         "skew, tile nonzeros, ticket streams): `steps` timed runs, one JSON line (for profiling)")
     args = ap.parse_args()
+    if args.only_config:
+        only_config(args)
+        return
     if args.probe:
         probe()
         return
@@ -670,10 +699,14 @@ def main():
     # ---- recursive level refinement (Sec. 4.4) on the same matrix and launch options ----
     recursion = {"unrefined": {"ms": round(ms, 4), "level_groups": G, "violating_groups": info["violating_groups"]}}
     if not args.only_main:
-        for sm in (1, 2):
+        # at the headline's budget, then at the small budget where refinement
+        # does best (level groups of at most about 1 MB), with one and with
+        # eight XCD ticket streams
+        for sm, cmb, streams in ((1, cfg["cache_mb"], 1), (2, cfg["cache_mb"], 1), (1, 20, 1), (1, 20, 8)):
+            key = f"s_m={sm}" + ("" if cmb == cfg["cache_mb"] else f"_C{cmb}MB") + ("_xcd8" if streams == 8 else "")
             t0 = time.time()
-            pr = Plan(A, p, cfg["cache_mb"] << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile_nnz"],
-                      recursion_stages=sm)
+            pr = Plan(A, p, cmb << 20, root_mode=1, skew=cfg["skew"], tile_nnz=cfg["tile_nnz"],
+                      recursion_stages=sm, xcd_streams=streams)
             ps = time.time() - t0
             rperm = pr.arrays()[0].astype(np.int64)
             Xr = torch.from_numpy(np.ascontiguousarray(x[rperm])).to(dev)
@@ -682,13 +715,14 @@ def main():
             Yr = np.empty((p, n))
             Yr[:, rperm] = Y.cpu().numpy()
             ri = pr.info()
-            recursion[f"s_m={sm}"] = {"ms": round(tr, 4), "gflops": round(flop / tr / 1e6, 1),
-                                      "vs_unrefined": round(ms / tr, 3), "units": ri["n_units"],
-                                      "max_stage": ri["max_stage"], "dep_ranges_per_tile":
-                                      round(ri["n_dep_ranges"] / ri["n_tiles"], 2), "plan_seconds": round(ps, 2),
-                                      "max_rel_diff_vs_unrefined": float(f"{max(rel_errs(Yr, Yh)):.3e}")}
+            recursion[key] = {"ms": round(tr, 4), "gflops": round(flop / tr / 1e6, 1),
+                              "vs_unrefined": round(ms / tr, 3), "vs_baseline": round(t_base / tr, 3),
+                              "units": ri["n_units"], "violating_groups": ri["violating_groups"],
+                              "max_stage": ri["max_stage"], "dep_ranges_per_tile":
+                              round(ri["n_dep_ranges"] / ri["n_tiles"], 2), "plan_seconds": round(ps, 2),
+                              "max_rel_diff_vs_unrefined": float(f"{max(rel_errs(Yr, Yh)):.3e}")}
             if ref is not None:
-                recursion[f"s_m={sm}"]["max_rel_err_vs_oracle"] = fmt(max(rel_errs(Yr, ref)))
+                recursion[key]["max_rel_err_vs_oracle"] = fmt(max(rel_errs(Yr, ref)))
             del pr, Xr
         # bulky levels: the same matrix from an interior root (vertex 0 of the
         # random relabelling), and a power-law graph whose BFS levels are few

@@ -92,7 +92,8 @@ typedef struct mpk_options {
                                  diagonals earlier (more work in flight without waiting, a
                                  reuse window of s*p + 1 groups instead of p + 1) */
     int32_t xcd_streams;      /* 1 (default): one ticket sequence for the whole grid.  8: the tiles
-                                 of every level group are cut into 8 slices and slice s is run by
+                                 of every level group (every unit of a refined plan) are cut into
+                                 8 slices and slice s is run by
                                  the workgroups with blockIdx % 8 == s, which share one XCD on
                                  MI355X (the dispatcher deals workgroups round-robin over the 8
                                  XCDs), so a tile meets the same L2 at every power */

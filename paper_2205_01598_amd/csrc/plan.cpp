@@ -448,6 +448,31 @@ struct Refiner {
     }
 };
 
+// Ticket streams.  With S > 1 the tiles of each level group (of each unit of
+// a refined plan) are cut into S consecutive slices (slice s = tiles whose
+// position in the group falls in [s/S, (s+1)/S)); stream s holds the tickets
+// of slice s in the order of hp.work.  A tile of a level reads the neighbour
+// levels at about the same relative position, so its dependencies mostly
+// stay in its own stream.  Every dependency is an earlier ticket of the
+// whole order, and each stream keeps that order, so the earliest unfinished
+// ticket is always at the head of its stream and can run.
+void split_streams(HostPlan &hp, int S) {
+    const int64_t T = (int64_t)hp.tile_group.size();
+    const int64_t G = (int64_t)hp.group_tile.size() - 1;
+    std::vector<int32_t> tile_stream(T, 0);
+    if (S > 1)
+        for (int64_t gi = 0; gi < G; ++gi) {
+            const int64_t t0 = hp.group_tile[gi], nt = hp.group_tile[gi + 1] - t0;
+            for (int64_t t = t0; t < t0 + nt; ++t) tile_stream[t] = (int32_t)(((t - t0) * S) / nt);
+        }
+    hp.stream_ptr.assign(S + 1, 0);
+    for (int32_t w : hp.work) hp.stream_ptr[tile_stream[w >> 6] + 1]++;
+    for (int sidx = 0; sidx < S; ++sidx) hp.stream_ptr[sidx + 1] += hp.stream_ptr[sidx];
+    hp.work_streams.assign(hp.work.size(), 0);
+    std::vector<int32_t> fill(hp.stream_ptr.begin(), hp.stream_ptr.end() - 1);
+    for (int32_t w : hp.work) hp.work_streams[fill[tile_stream[w >> 6]]++] = w;
+}
+
 constexpr int64_t kKeyUnit = 1 << 24;  // wavefront key of one stage-0 level group
 // Dependency ranges of a refined tile with at most this many tiles between
 // them are merged (the tiles between are waited for too): a wait polls its
@@ -467,7 +492,6 @@ constexpr int32_t kDepMergeGap = 31;
 // groups (key g*K) it is the order of the diagonal g + skew*q.
 mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &opt) {
     const int64_t n = hp.n;
-    if (opt.xcd_streams != 1) return fail(MPK_ERR_UNSUPPORTED, "a refined plan uses one ticket stream");
     int64_t tile_nnz = opt.tile_nnz > 0 ? opt.tile_nnz : 8192;
     const int64_t max_tile_rows = 1 << 14;
     hp.tile_nnz = (int32_t)tile_nnz;
@@ -589,9 +613,7 @@ mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &
     hp.work.clear();
     hp.work.reserve(tk.size());
     for (const auto &x : tk) hp.work.push_back(std::get<2>(x) * 64 + (std::get<1>(x) - 1));
-    hp.stream_ptr.assign(2, 0);
-    hp.stream_ptr[1] = (int32_t)hp.work.size();
-    hp.work_streams = hp.work;
+    split_streams(hp, opt.xcd_streams);
     return MPK_OK;
 }
 
@@ -832,27 +854,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
             for (int32_t t = hp.group_tile[gi]; t < hp.group_tile[gi + 1]; ++t) hp.work.push_back(t * 64 + (q - 1));
         }
 
-        // Ticket streams.  With 8 streams the tiles of each level group are
-        // cut into 8 consecutive slices (slice s = tiles whose position in the
-        // group falls in [s/8, (s+1)/8)); stream s holds the tickets of slice
-        // s in the order above.  A tile of a level reads the neighbour levels
-        // at about the same relative position, so its dependencies mostly
-        // stay in its own stream.
-        const int S = opt.xcd_streams;
-        std::vector<int32_t> tile_stream(T, 0);
-        if (S > 1)
-            for (int64_t gi = 0; gi < G; ++gi) {
-                const int64_t t0 = hp.group_tile[gi], nt = hp.group_tile[gi + 1] - t0;
-                for (int64_t t = t0; t < t0 + nt; ++t) tile_stream[t] = (int32_t)(((t - t0) * S) / nt);
-            }
-        hp.stream_ptr.assign(S + 1, 0);
-        for (int32_t w : hp.work) hp.stream_ptr[tile_stream[w >> 6] + 1]++;
-        for (int sidx = 0; sidx < S; ++sidx) hp.stream_ptr[sidx + 1] += hp.stream_ptr[sidx];
-        hp.work_streams.assign(hp.work.size(), 0);
-        {
-            std::vector<int32_t> fill(hp.stream_ptr.begin(), hp.stream_ptr.end() - 1);
-            for (int32_t w : hp.work) hp.work_streams[fill[tile_stream[w >> 6]]++] = w;
-        }
+        split_streams(hp, opt.xcd_streams);
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");
     }

@@ -81,6 +81,25 @@ def test_refined_matches_oracle(case):
         assert e <= TOL, f"power {q + 1}: rel err {e:.3e}"
 
 
+@pytest.mark.parametrize("case", ["27pt_p8_s2", "rgg"])
+@pytest.mark.parametrize("wg", [0, 40])
+def test_refined_xcd_streams_equal_single_stream(case, wg):
+    # eight ticket streams (workgroup b serves stream b % 8) give the same
+    # results as one stream, bit for bit
+    A, p, C, opts = _case(case)
+    opts = dict(opts)
+    opts.setdefault("recursion_stages", 1)
+    one = Plan(A, p, C, root_mode=1, workgroups=wg, **opts)
+    eight = Plan(A, p, C, root_mode=1, workgroups=wg, xcd_streams=8, **opts)
+    assert eight.info()["recursive"] == 1
+    x = W.uniform_vector(A.n, seed=13)
+    y8 = _run(eight, x, p)
+    assert np.array_equal(y8, _run(one, x, p))
+    ref = O.spmv_powers(A, x, p)
+    for q in range(p):
+        assert _rel_err(y8[q], ref[q]) <= TOL
+
+
 def test_refined_integer_bit_exact_and_fenced():
     A = W.integer_stencil_27pt(20, seed=5)
     rng = np.random.default_rng(5)

@@ -133,10 +133,21 @@ def test_refined_plan_without_violations_is_unrefined():
     assert np.array_equal(pl.arrays()[0], fp)
 
 
+def test_refined_plan_xcd_streams_keep_the_order():
+    # eight ticket streams slice the tiles of every unit; the tiles and the
+    # ticket order of the plan stay those of the single-stream plan
+    A, p, C = _case("2d5pt")
+    one = Plan(A, p, C, upload=False, recursion_stages=1)
+    eight = Plan(A, p, C, upload=False, recursion_stages=1, xcd_streams=8)
+    assert eight.info()["recursive"] == 1
+    for a, b in zip(one.tiles(), eight.tiles()):
+        assert np.array_equal(a, b)
+    for a, b in zip(one.units(), eight.units()):
+        assert np.array_equal(a, b)
+
+
 def test_refined_plan_rejections():
     A, p, C = _case("2d5pt")
-    with pytest.raises(MpkError):
-        Plan(A, p, C, upload=False, recursion_stages=1, xcd_streams=8)
     with pytest.raises(MpkError):
         Plan(A, p, C, upload=False, recursion_stages=-1)
     with pytest.raises(MpkError):
