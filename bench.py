@@ -167,26 +167,6 @@ def bench_small_2d(torch, Plan, W, dev):
             "parity": parity}
 
 
-def vendor_spmv(torch, plan, X, Y, own_ms):
-    """Context for the baseline's quality: torch's sparse CSR matrix-vector
-    product (hipSPARSE / rocSPARSE on ROCm) on the same renumbered matrix,
-    timed like one SpMV of the baseline, and its largest relative difference
-    from the library's first power."""
-    rp, col, val = plan.matrix()
-    dev = X.device
-    A = torch.sparse_csr_tensor(torch.from_numpy(rp.astype(np.int32)).to(dev),
-                                torch.from_numpy(col).to(dev), torch.from_numpy(val).to(dev),
-                                size=(plan.n, plan.n))
-    del rp, col, val
-    plan.run_baseline(X, Y)
-    y = torch.mv(A, X)
-    diff = float(((y - Y[0]).abs().max() / Y[0].abs().max()).item())
-    ms = timed(torch, lambda: torch.mv(A, X), 20, 3)
-    del A, y
-    return {"library": "torch.sparse CSR mv (hipSPARSE)", "ms": round(ms, 4), "own_spmv_ms": round(own_ms, 4),
-            "own_speedup": round(ms / own_ms, 3), "max_rel_diff_vs_own": fmt(diff)}
-
-
 def only_config(args):
     """The headline matrix in one plan configuration, `steps` timed runs after
     `warmup` (rocprofv3 runs of a single configuration)."""
@@ -616,13 +596,6 @@ def main():
     base["bfs_order"] = timed(torch, lambda: plan.run_baseline(X, Y), 10, 3)
     t_base = min(base.values())
     log(f"baselines (ms): {base}")
-    vendor = None
-    if not args.only_main:
-        try:
-            vendor = vendor_spmv(torch, plan, X, Y, t_base / p)
-        except RuntimeError as e:  # a library the bench only quotes for context
-            vendor = {"error": str(e)[:200]}
-        log(f"vendor SpMV: {vendor}")
 
     # ---- MPK configuration: small sweep on the same levels ------------------------
     cands = [dict(cache_mb=256, skew=2, tile_nnz=8192), dict(cache_mb=256, skew=2, tile_nnz=6144),
@@ -852,7 +825,6 @@ def main():
         "per_call_timing": per_call,
         "baseline_ms": {k: round(v, 4) for k, v in base.items()},
         "baseline_gflops": round(flop / t_base / 1e6, 1),
-        "vendor_spmv": vendor,
         # the bytes p SpMVs move (matrix p times), per MPK time, and the
         # baseline's own rate: what the level blocking turns into speed
         "effective_GBps_as_p_spmvs": {"mpk": round(p * spmv_bytes(n, nnz) / (ms * 1e-3) / 1e9, 1),
