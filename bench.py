@@ -49,9 +49,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
-    """HBM-side bytes per launch from the committed counter summary, if it was
-    taken on the kernel sources as they are now (else None)."""
+def profiled_traffic(key: str = "traffic_bytes_per_launch"):
+    """HBM-side bytes per launch from the committed counter summary (the MPK
+    kernel's, or with key spmv_traffic_bytes_per_launch one baseline SpMV's),
+    if it was taken on the kernel sources as they are now (else None)."""
     try:
         kv = {}
         with open(PROFILE) as fh:
@@ -61,9 +62,23 @@ def profiled_traffic():
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_source_hash") != kernel_source_hash():
             return None
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def code_balance(n, nnz, p):
+    """Code balance B_C (Sec. 3): bytes moved per flop, 2 nnz flops per SpMV.
+    Algorithmic (matrix once, x, p outputs) and measured from the profiled
+    L2-to-fabric traffic, for the MPK and for p baseline SpMVs; None where no
+    profile of the current sources exists."""
+    flops = 2.0 * nnz * p
+    t_mpk, t_spmv = profiled_traffic(), profiled_traffic("spmv_traffic_bytes_per_launch")
+    return {"algorithmic_mpk": round(mpk_bytes(n, nnz, p) / flops, 4),
+            "algorithmic_p_spmvs": round(p * spmv_bytes(n, nnz) / flops, 4),
+            "measured_mpk": None if t_mpk is None else round(t_mpk / flops, 4),
+            "measured_p_spmvs": None if t_spmv is None else round(p * t_spmv / flops, 4),
+            "unit": "bytes/flop"}
 
 
 def log(msg):
@@ -844,6 +859,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                      "kernel": "mpk_persistent", "algorithmic_bytes": alg_bytes},
+        "code_balance": code_balance(n, nnz, p),
         "cpu_baseline": cpu,
         "other_workloads": extra,
     }
