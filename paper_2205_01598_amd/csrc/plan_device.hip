@@ -259,7 +259,8 @@ struct DeviceGraph {
     int64_t *ptr = nullptr;
     int32_t *adj = nullptr, *owner = nullptr, *order = nullptr, *local = nullptr, *blocksum = nullptr,
             *scalar = nullptr, *level_end = nullptr, *cnt = nullptr;
-    uint32_t *seen = nullptr;
+    uint32_t *seen = nullptr, *bk_seen = nullptr;
+    int32_t *bk_order = nullptr, *bk_owner = nullptr;  // the root's sweep while a candidate is tried
     Frontier *front = nullptr;
     unsigned long long *key = nullptr;
     std::vector<void *> allocs;
@@ -351,6 +352,9 @@ mpk_status alloc_bfs(DeviceGraph &g) {
     LV_TRY(dalloc(g, &g.level_end, n + 1));
     LV_TRY(dalloc(g, &g.cnt, n));
     LV_TRY(dalloc(g, &g.seen, (n + 31) / 32));
+    LV_TRY(dalloc(g, &g.bk_seen, (n + 31) / 32));
+    LV_TRY(dalloc(g, &g.bk_order, n));
+    LV_TRY(dalloc(g, &g.bk_owner, n));
     LV_TRY(dalloc(g, &g.front, 1));
     return MPK_OK;
 }
@@ -361,6 +365,7 @@ mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, s
 
     // ---- root: vertex 0, or George-Liu from vertex 0 -------------------------------
     int32_t root = 0;
+    std::vector<int32_t> lp_root;  // level ends of the root's component (search sweeps)
     if (root_mode == 1) {
         std::vector<int32_t> lp;
         auto sweep = [&](int32_t r, int64_t *ecc) -> mpk_status {
@@ -376,6 +381,7 @@ mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, s
         int64_t ecc = 0;
         mpk_status st = sweep(root, &ecc);
         if (st != MPK_OK) return st;
+        lp_root = lp;
         for (;;) {
             const unsigned long long init = ~0ull;
             LV_TRY(hipMemcpy(g.key, &init, sizeof(init), hipMemcpyHostToDevice));
@@ -386,12 +392,23 @@ mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, s
             unsigned long long key = 0;
             LV_TRY(hipMemcpy(&key, g.key, sizeof(key), hipMemcpyDeviceToHost));
             const int32_t cand = (int32_t)(key & 0xffffffffu);
+            // the root's sweep is kept: a candidate that is no better is
+            // undone instead of sweeping from the root once more
+            LV_TRY(hipMemcpyAsync(g.bk_order, g.order, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, 0));
+            LV_TRY(hipMemcpyAsync(g.bk_owner, g.owner, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, 0));
+            LV_TRY(hipMemcpyAsync(g.bk_seen, g.seen, sizeof(uint32_t) * ((n + 31) / 32), hipMemcpyDeviceToDevice,
+                                  0));
             int64_t e2 = 0;
             if ((st = sweep(cand, &e2)) != MPK_OK) return st;
             if (e2 > ecc) {
                 root = cand;
                 ecc = e2;
+                lp_root = lp;
             } else {
+                LV_TRY(hipMemcpyAsync(g.order, g.bk_order, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, 0));
+                LV_TRY(hipMemcpyAsync(g.owner, g.bk_owner, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, 0));
+                LV_TRY(hipMemcpyAsync(g.seen, g.bk_seen, sizeof(uint32_t) * ((n + 31) / 32),
+                                      hipMemcpyDeviceToDevice, 0));
                 break;
             }
         }
@@ -400,10 +417,17 @@ mpk_status bfs_on_device(DeviceGraph &g, int32_t root_mode, int64_t *root_out, s
 
     // ---- levels of the whole graph: root's component, then the others --------------
     mpk_status st;
-    if ((st = reset_owner(g)) != MPK_OK) return st;
-    if ((st = place_root(g, 0, root)) != MPK_OK) return st;
     int64_t pos = 0;
-    if ((st = expand_component(g, 0, level_ptr, &pos)) != MPK_OK) return st;
+    if (root_mode == 1) {
+        // the root's component is numbered already, by the search's sweep
+        // from it (the same expansion from the same state)
+        level_ptr.insert(level_ptr.end(), lp_root.begin() + 1, lp_root.end());
+        pos = lp_root.back();
+    } else {
+        if ((st = reset_owner(g)) != MPK_OK) return st;
+        if ((st = place_root(g, 0, root)) != MPK_OK) return st;
+        if ((st = expand_component(g, 0, level_ptr, &pos)) != MPK_OK) return st;
+    }
     while (pos < n) {
         const int32_t none = (int32_t)n;
         LV_TRY(hipMemcpy(g.scalar, &none, sizeof(int32_t), hipMemcpyHostToDevice));
