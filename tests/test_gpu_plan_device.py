@@ -228,3 +228,27 @@ def test_device_resident_rejections():
     # the same plan is still made from good arrays afterwards
     pl = Plan.from_device(rp, col, val, 2, 1 << 20)
     assert pl.info()["n"] == A.n
+
+
+def test_device_resident_chebyshev_step_equals_host_plan():
+    # the recurrence epilogue (two columns, complex coefficients) on a plan
+    # made from device memory: a Chebyshev step equals the host plan's bit
+    # for bit, also with a remainder block (degree 12, p = 5)
+    from paper_2205_01598_amd.cheb import ChebPropagator
+
+    dev = _dev()
+    A = W.anderson_3d(20, seed=3)
+    x = W.random_phase_state(A.n, seed=3)
+    for p, M in ((8, 16), (5, 12)):
+        host = Plan(A, p, 1 << 20, root_mode=1, nrhs=2, skew=2, tile_nnz=1024)
+        res = Plan.from_device(*_to_dev(A, dev), p, 1 << 20, root_mode=1, nrhs=2, skew=2, tile_nnz=1024)
+        assert np.array_equal(res.arrays()[0], host.arrays()[0])
+        perm = host.arrays()[0].astype(np.int64)
+        X = torch.from_numpy(np.ascontiguousarray(x[perm])).to(dev)
+        outs = []
+        for pl in (host, res):
+            acc = torch.full_like(X, float("nan"))
+            ChebPropagator.schroedinger(pl, M, 4.0).step(X, acc)
+            pl.status()
+            outs.append(acc.cpu().numpy().view(np.int64))
+        assert np.array_equal(outs[0], outs[1])
