@@ -274,37 +274,58 @@ int64_t bfs_component(const Graph &g, int64_t root, int64_t start, std::vector<i
     return a;
 }
 
-// George-Liu pseudo-peripheral search from `start`: move to the
-// smallest-degree vertex (lowest index on ties) of the farthest level while
-// that raises the eccentricity.
-int64_t peripheral_root(const Graph &g, int64_t n, int64_t start) {
-    std::vector<int32_t> order(n), owner(n), lptr;
+// Every further component from its smallest unnumbered original index, at
+// the next level, after the components already numbered up to `pos`.
+void remaining_components(const Graph &g, int64_t n, int64_t pos, std::vector<int32_t> &perm,
+                          std::vector<int32_t> &owner, std::vector<int32_t> &level_ptr, std::vector<int64_t> &cnt) {
+    int64_t scan = 0;
+    while (pos < n) {
+        while (owner[scan] != INT32_MAX) ++scan;
+        pos = bfs_component(g, scan, pos, perm, owner, level_ptr, cnt);
+    }
+}
+
+// George-Liu pseudo-peripheral search from `start` (move to the
+// smallest-degree vertex, lowest index on ties, of the farthest level while
+// that raises the eccentricity), then the levels of the whole graph from
+// that root.  The search's sweep from the chosen root is its component's
+// levels already (the same expansion from the same state): it is kept, and
+// a candidate's sweep that does not raise the eccentricity is dropped.
+void peripheral_levels(const Graph &g, int64_t n, int64_t start, int64_t *root_out, std::vector<int32_t> &perm,
+                       std::vector<int32_t> &level_ptr) {
+    perm.assign(n, 0);
+    level_ptr.assign(1, 0);
+    *root_out = 0;
+    if (n == 0) return;
+    std::vector<int32_t> owner(n), order2(n), owner2(n), lptr2;
     std::vector<int64_t> cnt;
-    auto sweep = [&](int64_t r) {
-        std::fill(owner.begin(), owner.end(), INT32_MAX);
-        lptr.assign(1, 0);
-        bfs_component(g, r, 0, order, owner, lptr, cnt);
-        return (int64_t)lptr.size() - 2;  // eccentricity = levels - 1
+    auto sweep = [&](int64_t r, std::vector<int32_t> &order, std::vector<int32_t> &own, std::vector<int32_t> &lp) {
+        std::fill(own.begin(), own.end(), INT32_MAX);
+        lp.assign(1, 0);
+        bfs_component(g, r, 0, order, own, lp, cnt);
+        return (int64_t)lp.size() - 2;  // eccentricity = levels - 1
     };
     int64_t r = start;
-    int64_t ecc = sweep(r);
+    int64_t ecc = sweep(r, perm, owner, level_ptr);
     for (;;) {
         int64_t best = -1, bestdeg = 0;
-        for (int64_t i = lptr[lptr.size() - 2]; i < lptr.back(); ++i) {
-            const int64_t v = order[i], d = g.deg(v);
+        for (int64_t i = level_ptr[level_ptr.size() - 2]; i < level_ptr.back(); ++i) {
+            const int64_t v = perm[i], d = g.deg(v);
             if (best < 0 || d < bestdeg || (d == bestdeg && v < best)) {
                 best = v;
                 bestdeg = d;
             }
         }
-        const int64_t e2 = sweep(best);
-        if (e2 > ecc) {
-            r = best;
-            ecc = e2;
-        } else {
-            return r;
-        }
+        const int64_t e2 = sweep(best, order2, owner2, lptr2);
+        if (e2 <= ecc) break;
+        r = best;
+        ecc = e2;
+        perm.swap(order2);
+        owner.swap(owner2);
+        level_ptr.swap(lptr2);
     }
+    *root_out = r;
+    remaining_components(g, n, level_ptr.back(), perm, owner, level_ptr, cnt);
 }
 
 // Levels of the whole graph: the root's component first, then each further
@@ -316,12 +337,8 @@ void bfs_levels(const Graph &g, int64_t n, int64_t root, std::vector<int32_t> &p
     if (n == 0) return;
     std::vector<int32_t> owner(n, INT32_MAX);
     std::vector<int64_t> cnt;
-    int64_t pos = bfs_component(g, root, 0, perm, owner, level_ptr, cnt);
-    int64_t scan = 0;
-    while (pos < n) {
-        while (owner[scan] != INT32_MAX) ++scan;
-        pos = bfs_component(g, scan, pos, perm, owner, level_ptr, cnt);
-    }
+    const int64_t pos = bfs_component(g, root, 0, perm, owner, level_ptr, cnt);
+    remaining_components(g, n, pos, perm, owner, level_ptr, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,8 +1070,10 @@ mpk_status build_host_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes,
                 st = device_bfs_levels(n, g.ptr.data(), g.adj.data(), opt.root_mode, &hp.root, hp.perm, hp.level_ptr);
                 if (st != MPK_OK) return st;
             } else {
-                if (n > 0 && opt.root_mode == 1) hp.root = peripheral_root(g, n, 0);
-                bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
+                if (opt.root_mode == 1)
+                    peripheral_levels(g, n, 0, &hp.root, hp.perm, hp.level_ptr);
+                else
+                    bfs_levels(g, n, hp.root, hp.perm, hp.level_ptr);
             }
             if (opt.recursion_stages > 0 && n > 0) {
                 // Sec. 4.4: refine maximal runs of groups that violate Eq. (5)
