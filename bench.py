@@ -182,6 +182,28 @@ def bench_small_2d(torch, Plan, W, dev):
             "parity": parity}
 
 
+def plan_device_only(args):
+    """Plans the headline matrix from its CSR in device memory twice (the
+    second one timed), for a kernel trace of the device planner."""
+    import torch
+
+    import workloads as W
+    from paper_2205_01598_amd import Plan
+
+    A, _ = W.stencil_27pt_random(args.n, seed=args.seed)
+    dA = [torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (A.rowptr, A.col, A.val)]
+    secs = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        pl = Plan.from_device(*dA, args.p, 256 << 20, root_mode=1)
+        torch.cuda.synchronize()
+        secs.append(time.time() - t0)
+    inf = pl.info()
+    print(json.dumps({"plan_seconds": [round(v, 4) for v in secs], "levels": inf["n_levels"],
+                      "phase_seconds": [round(v, 4) for v in inf["phase_seconds"]]}), flush=True)
+
+
 def only_config(args):
     """The headline matrix in one plan configuration, `steps` timed runs after
     `warmup` (rocprofv3 runs of a single configuration)."""
@@ -532,7 +554,12 @@ def main():
     ap.add_argument("--only-config", default=None, metavar="S_M,C_MB,SKEW,TILE,STREAMS",
                     help="only the headline matrix in this plan configuration (recursion stages, budget in MB, "
                          "skew, tile nonzeros, ticket streams): `steps` timed runs, one JSON line (for profiling)")
+    ap.add_argument("--plan-device-only", action="store_true",
+                    help="only planning the headline matrix from device memory (twice), one JSON line (for profiling)")
     args = ap.parse_args()
+    if args.plan_device_only:
+        plan_device_only(args)
+        return
     if args.only_config:
         only_config(args)
         return

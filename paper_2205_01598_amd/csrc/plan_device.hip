@@ -772,11 +772,18 @@ __global__ void check_rowptr(const int64_t *__restrict__ rp, int64_t n, int64_t 
     if (m) atomicMax(longest, m);
 }
 
-// check_pattern: a group of 32 lanes per row, one stored entry per lane; the
-// transposed entry is found by a binary search in row v.
-__global__ void check_pattern(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
-                              int64_t nnz, int32_t *bad) {
+// check_pattern: a group of 32 lanes per row, one stored entry per lane.
+// Symmetry: every distinct entry (u, v) above the diagonal must have its
+// transpose, found by a binary search in row v, and the distinct entries
+// above and below the diagonal must be equally many (updown[0], updown[1]);
+// the map (u, v) -> (v, u) is then a bijection between the two sets.  The
+// repeats of a sorted row are skipped; an unsorted row is reported anyway.
+__global__ void __launch_bounds__(kThreads)
+    check_pattern(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n, int64_t nnz,
+                  int32_t *bad, unsigned long long *updown) {
+    __shared__ unsigned long long s_up[kThreads], s_down[kThreads];
     int32_t flags = 0;
+    unsigned long long up = 0, down = 0;
     for (int64_t slot = blockIdx.x * (int64_t)kThreads + threadIdx.x; slot < n * kLanes;
          slot += (int64_t)gridDim.x * kThreads) {
         const int64_t u = slot / kLanes;
@@ -788,8 +795,17 @@ __global__ void check_pattern(const int64_t *__restrict__ rp, const int32_t *__r
                 flags |= 2;
                 continue;
             }
-            if (j > a && col[j - 1] > v) flags |= 4;
+            if (j > a) {
+                const int32_t prev = col[j - 1];
+                if (prev > v) flags |= 4;
+                if (prev == v) continue;  // a repeat
+            }
+            if (v < u) {
+                ++down;
+                continue;
+            }
             if (v == u) continue;
+            ++up;
             int64_t lo = rp[v], hi = rp[v + 1];
             if (lo < 0 || lo > hi || hi > nnz) continue;  // reported by check_rowptr
             const int64_t end = hi;
@@ -802,6 +818,20 @@ __global__ void check_pattern(const int64_t *__restrict__ rp, const int32_t *__r
         }
     }
     if (flags) atomicOr(bad, flags);
+    s_up[threadIdx.x] = up;
+    s_down[threadIdx.x] = down;
+    __syncthreads();
+    for (int d = kThreads / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            s_up[threadIdx.x] += s_up[threadIdx.x + d];
+            s_down[threadIdx.x] += s_down[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(updown, s_up[0]);
+        atomicAdd(updown + 1, s_down[0]);
+    }
 }
 
 __global__ void narrow_rowptr(const int64_t *__restrict__ in, int64_t n1, int32_t *__restrict__ out) {
@@ -950,22 +980,24 @@ mpk_status device_plan_resident(const mpk_csr *A, int32_t root_mode, int64_t *ro
     g.n = n;
     int32_t *flag = nullptr;
     int64_t *cnt = nullptr;
-    unsigned long long *mx = nullptr;
+    unsigned long long *mx = nullptr;  // longest row, entries above and below the diagonal
     LV_TRY(dalloc(g, &flag, 1));
     LV_TRY(dalloc(g, &cnt, n));
-    LV_TRY(dalloc(g, &mx, 1));
+    LV_TRY(dalloc(g, &mx, 3));
     // ---- validation (the host planner's checks) and the pattern ----------------------
     const int32_t zero = 0;
-    const unsigned long long zero64 = 0;
+    const unsigned long long zero64[3] = {0, 0, 0};
     LV_TRY(hipMemcpy(flag, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
-    LV_TRY(hipMemcpy(mx, &zero64, sizeof(zero64), hipMemcpyHostToDevice));
+    LV_TRY(hipMemcpy(mx, zero64, sizeof(zero64), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(check_rowptr, dim3(2048), dim3(kThreads), 0, 0, drp, n, nnz, flag, mx);
-    hipLaunchKernelGGL(check_pattern, dim3(8192), dim3(kThreads), 0, 0, drp, dcol, n, nnz, flag);
+    hipLaunchKernelGGL(check_pattern, dim3(8192), dim3(kThreads), 0, 0, drp, dcol, n, nnz, flag, mx + 1);
     LV_TRY(hipGetLastError());
     int32_t bad = 0;
-    unsigned long long longest = 0;
+    unsigned long long counts[3] = {0, 0, 0};
     LV_TRY(hipMemcpy(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost));
-    LV_TRY(hipMemcpy(&longest, mx, sizeof(longest), hipMemcpyDeviceToHost));
+    LV_TRY(hipMemcpy(counts, mx, sizeof(counts), hipMemcpyDeviceToHost));
+    const unsigned long long longest = counts[0];
+    if (counts[1] != counts[2]) bad |= 8;
     if (bad & 1) return fail(MPK_ERR_CSR, "device CSR: row pointers not monotone or not in [0, nnz]");
     if (bad & 2) return fail(MPK_ERR_CSR, "device CSR: column index out of range");
     if ((int64_t)longest > kResidentRowMax)
