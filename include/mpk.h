@@ -81,7 +81,10 @@ typedef struct mpk_options {
     int32_t val_dtype;        /* mpk_dtype of stored matrix values (default MPK_F64) */
     int32_t nrhs;             /* k, right-hand sides per run, 1..MPK_MAX_NRHS (default 1) */
     int32_t workgroups;       /* persistent-kernel grid size; 0 = automatic */
-    int32_t tile_nnz;         /* target nonzeros per device tile; 0 = 8192 */
+    int32_t tile_nnz;         /* target nonzeros per device tile; 0 = 8192.  At or
+                                 above one kernel chunk (4096 nonzeros at nrhs = 1,
+                                 2048/nrhs otherwise) a tile is a run of
+                                 round(tile_nnz / chunk) whole chunks */
     int32_t reserved0;        /* must be 0 */
     int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row

@@ -4,8 +4,8 @@
 // level-blocked MPK (Sec. 4): chunk_pass computes y = A x on a contiguous
 // range of rows (k right-hand sides, row-major N x k vectors), with an
 // optional three-term recurrence epilogue (Sec. 7).  The rows are cut into
-// chunks of at most chunk_nnz(k) stored nonzeros.  Phase 1: every thread
-// forms kProdPerThread of the chunk's k-column products (nonzero j, column c
+// chunks of at most chunk_nnz(k, NP) stored nonzeros.  Phase 1: every thread
+// forms NP of the chunk's k-column products (nonzero j, column c
 // flattened with c fastest), issuing all its val/col loads and then all its
 // gathers without waiting in between, and writes them to LDS together with
 // the chunk's row pointers.  Phase 2: after a barrier, a thread sums one
@@ -103,14 +103,17 @@ __device__ __forceinline__ void put(double *p, double v) {
         *p = v;
 }
 
-constexpr int kProdPerThread = 8;  // products per thread and chunk
+static_assert(kBlock == 256, "the chunk lengths of mpk_internal.h assume 256 threads per workgroup");
 
-// nonzeros per chunk for k right-hand sides: kBlock * kProdPerThread products
-// (16 KB of LDS in FP64) whatever k is
-__host__ __device__ constexpr int chunk_nnz(int K) { return kBlock * kProdPerThread / K; }
-template <typename VT, int K>
+// nonzeros per chunk for k right-hand sides at NP products per thread:
+// kBlock * NP products (NP * 2 KB of LDS in FP64).  The persistent MPK kernel
+// and the bulk-synchronous kernels run on the plan's tile chunks with
+// NP = mpk_products_per_thread(k), the baseline SpMV on chunks of its own
+// with NP = spmv_products_per_thread(k).
+__host__ __device__ constexpr int chunk_nnz(int K, int NP) { return kBlock * NP / K; }
+template <typename VT, int K, int NP>
 struct ChunkLds {
-    typename AccumType<VT>::T prod[chunk_nnz(K) * K];
+    typename AccumType<VT>::T prod[kBlock * NP];
     int32_t rb[kChunkRows + 1];  // row pointers of the chunk's rows
 };
 
@@ -222,19 +225,19 @@ __device__ __forceinline__ void store_col2(int64_t r, int c, double v, const Col
 }
 
 // Registers of one chunk between its matrix loads and its gathers.
-template <typename VT, int K>
+template <typename VT, int K, int NP>
 struct ChunkRegs {
     static constexpr int NRB = (kChunkRows + 1 + kBlock - 1) / kBlock;
-    int cj[kProdPerThread];
-    typename AccumType<VT>::T a[kProdPerThread];
+    int cj[NP];
+    typename AccumType<VT>::T a[NP];
     int rbv[NRB];
 };
 
-// A chunk of the common kind: at least one and at most chunk_nnz(K) stored
-// nonzeros (uniform test).
-template <int K>
+// A chunk of the common kind: at least one and at most chunk_nnz(K, NP)
+// stored nonzeros (uniform test).
+template <int K, int NP>
 __device__ __forceinline__ bool plain_chunk(const int4 d) {
-    return d.w > d.z && d.w - d.z <= chunk_nnz(K);
+    return d.w > d.z && d.w - d.z <= chunk_nnz(K, NP);
 }
 
 // Phase 1, first half, of a plain chunk d = (r0, r1, j0, j1): the row
@@ -243,18 +246,18 @@ __device__ __forceinline__ bool plain_chunk(const int4 d) {
 // whose product phase 2 never reads), so they are all in flight together.
 // Nothing here depends on vector data: a caller may issue these loads
 // before it has waited for the vector the chunk multiplies.
-template <typename VT, int K>
+template <typename VT, int K, int NP>
 __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restrict__ rowptr,
                                            const int32_t *__restrict__ col, const VT *__restrict__ val,
-                                           ChunkRegs<VT, K> &g) {
+                                           ChunkRegs<VT, K, NP> &g) {
     using AT = typename AccumType<VT>::T;
     const int tid = threadIdx.x;
     const int nr = d.y - d.x;
 #pragma unroll
-    for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
+    for (int m = 0; m < ChunkRegs<VT, K, NP>::NRB; ++m)
         if (m * kBlock <= nr) g.rbv[m] = rowptr[d.x + min(tid + m * kBlock, nr)];
 #pragma unroll
-    for (int m = 0; m < kProdPerThread; ++m) {
+    for (int m = 0; m < NP; ++m) {
         const int pidx = tid + m * kBlock;
         const int jc = min(d.z + pidx / K, d.w - 1);
         g.cj[m] = col[jc];
@@ -265,21 +268,21 @@ __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restri
 // The gathers of a plain chunk (and, for k = 2 with the recurrence, the
 // epilogue operands of the calling thread's first output), issued without
 // waiting, so a caller may issue the next chunk's matrix loads behind them.
-template <typename VT, int K>
+template <typename VT, int K, int NP>
 struct ChunkGather {
-    typename AccumType<VT>::T xv[kProdPerThread];
+    typename AccumType<VT>::T xv[NP];
     Col2Ops pre, pre2;  // epilogue operands of outputs tid and tid + kBlock (k = 2, recurrence)
 };
 
-template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
+template <typename VT, int K, bool REC, bool COH, int NP>
+__device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K, NP> &g, const double *__restrict__ x,
                                              int q, const double *__restrict__ yq2, const RecArgs &rec,
-                                             ChunkGather<VT, K> &gx) {
+                                             ChunkGather<VT, K, NP> &gx) {
     using AT = typename AccumType<VT>::T;
     const int tid = threadIdx.x;
     const int nr = d.y - d.x;
 #pragma unroll
-    for (int m = 0; m < kProdPerThread; ++m) gx.xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
+    for (int m = 0; m < NP; ++m) gx.xv[m] = (AT)x[(int64_t)g.cj[m] * K + ((tid + m * kBlock) % K)];
     gx.pre = Col2Ops{};
     gx.pre2 = Col2Ops{};
     if constexpr (K == 2 && REC) {
@@ -292,38 +295,37 @@ __device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K
     }
 }
 
-template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K> &g, const ChunkGather<VT, K> &gx,
+template <typename VT, int K, bool REC, bool COH, int NP>
+__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K, NP> &g, const ChunkGather<VT, K, NP> &gx,
                                              const double *__restrict__ x, double *__restrict__ y, int q,
                                              const double *__restrict__ yq2, const RecArgs &rec,
-                                             ChunkLds<VT, K> &lds);
+                                             ChunkLds<VT, K, NP> &lds);
 
 // The rest of a plain chunk: gathers of x, products and row pointers to LDS,
 // then phase 2 (one thread per row for k = 1, per (row, column) for k >= 2,
 // stored order, four products read ahead) and the epilogue.
-template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K> &g, const double *__restrict__ x,
+template <typename VT, int K, bool REC, bool COH, int NP>
+__device__ __forceinline__ void chunk_finish(const int4 d, const ChunkRegs<VT, K, NP> &g, const double *__restrict__ x,
                                              double *__restrict__ y, int q, const double *__restrict__ yq2,
-                                             const RecArgs &rec, ChunkLds<VT, K> &lds) {
-    ChunkGather<VT, K> gx;
-    chunk_gather<VT, K, REC, COH>(d, g, x, q, yq2, rec, gx);
-    chunk_reduce<VT, K, REC, COH>(d, g, gx, x, y, q, yq2, rec, lds);
+                                             const RecArgs &rec, ChunkLds<VT, K, NP> &lds) {
+    ChunkGather<VT, K, NP> gx;
+    chunk_gather<VT, K, REC, COH, NP>(d, g, x, q, yq2, rec, gx);
+    chunk_reduce<VT, K, REC, COH, NP>(d, g, gx, x, y, q, yq2, rec, lds);
 }
 
-template <typename VT, int K, bool REC, bool COH>
-__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K> &g, const ChunkGather<VT, K> &gx,
+template <typename VT, int K, bool REC, bool COH, int NP>
+__device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K, NP> &g, const ChunkGather<VT, K, NP> &gx,
                                              const double *__restrict__ x, double *__restrict__ y, int q,
                                              const double *__restrict__ yq2, const RecArgs &rec,
-                                             ChunkLds<VT, K> &lds) {
+                                             ChunkLds<VT, K, NP> &lds) {
     using AT = typename AccumType<VT>::T;
-    constexpr int NP = kProdPerThread;
     const int tid = threadIdx.x;
     const int r0 = d.x, j0 = d.z;
     const int nr = d.y - d.x;
     const AT *xv = gx.xv;
     const Col2Ops &pre = gx.pre, &pre2 = gx.pre2;
 #pragma unroll
-    for (int m = 0; m < ChunkRegs<VT, K>::NRB; ++m)
+    for (int m = 0; m < ChunkRegs<VT, K, NP>::NRB; ++m)
         if (m * kBlock <= nr && tid + m * kBlock <= nr) lds.rb[tid + m * kBlock] = g.rbv[m];
 #pragma unroll
     for (int m = 0; m < NP; ++m) lds.prod[tid + m * kBlock] = g.a[m] * xv[m];
@@ -402,22 +404,22 @@ __device__ __forceinline__ void chunk_reduce(const int4 d, const ChunkRegs<VT, K
 }
 
 // One chunk d = (r0, r1, j0, j1): rows [r0, r1) with stored nonzeros
-// [j0, j1), at most chunk_nnz(K) of them and at most kChunkRows rows, or a
+// [j0, j1), at most chunk_nnz(K, NP) of them and at most kChunkRows rows, or a
 // single longer row.
-template <typename VT, int K, bool REC, bool COH>
+template <typename VT, int K, bool REC, bool COH, int NP>
 __device__ __forceinline__ void chunk_pass(const int4 d, const int32_t *__restrict__ rowptr,
                                            const int32_t *__restrict__ col, const VT *__restrict__ val,
                                            const double *__restrict__ x, double *__restrict__ y, int q,
                                            const double *__restrict__ yq2, const RecArgs &rec,
-                                           ChunkLds<VT, K> &lds) {
+                                           ChunkLds<VT, K, NP> &lds) {
     using AT = typename AccumType<VT>::T;
     static_assert(K == 1 || K == 2 || !REC, "the recurrence epilogue handles k <= 2");
     const int tid = threadIdx.x;
     const int r0 = d.x, r1 = d.y, j0 = d.z, j1 = d.w;
-    if (plain_chunk<K>(d)) {
-        ChunkRegs<VT, K> g;
-        chunk_load<VT, K>(d, rowptr, col, val, g);
-        chunk_finish<VT, K, REC, COH>(d, g, x, y, q, yq2, rec, lds);
+    if (plain_chunk<K, NP>(d)) {
+        ChunkRegs<VT, K, NP> g;
+        chunk_load<VT, K, NP>(d, rowptr, col, val, g);
+        chunk_finish<VT, K, REC, COH, NP>(d, g, x, y, q, yq2, rec, lds);
     } else if (j1 == j0) {  // rows without stored entries: y = 0 (uniform branch)
         for (int r = r0 + tid; r < r1; r += kBlock) {
             double v[K];

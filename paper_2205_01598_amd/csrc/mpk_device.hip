@@ -53,6 +53,9 @@ struct mpk_plan {
     int32_t *d_tile_row = nullptr, *d_trec = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_chunk = nullptr, *d_tile_chunk = nullptr, *d_dep3 = nullptr;  // d_chunk: int4 per chunk
+    // the baseline SpMV's own chunks of the whole matrix (spmv_chunk_nnz)
+    int32_t *d_chunk_spmv = nullptr;
+    int32_t n_chunks_spmv = 0;
     int32_t *d_dep3x = nullptr;
     int32_t *d_dep_ptr = nullptr, *d_dep_rng = nullptr;  // refined plans: per-tile range lists
     uint32_t *d_flags = nullptr, *d_ctrl = nullptr;
@@ -200,19 +203,19 @@ __global__ void convert_values_kernel(const double *__restrict__ src, int64_t n,
 // kernels
 // ----------------------------------------------------------------------------
 
-// Rows of chunks [c0, c1), one chunk after another.
-template <typename VT, int K, bool REC, bool COH>
+// Rows of chunks [c0, c1), one chunk after another, NP products per thread.
+template <typename VT, int K, bool REC, bool COH, int NP>
 __device__ __forceinline__ void chunks_body(int c0, int c1, const int4 *__restrict__ chunk,
                                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                             const VT *__restrict__ val, const double *__restrict__ x,
                                             double *__restrict__ y, int q, const double *__restrict__ yq2,
                                             const RecArgs &rec) {
-    __shared__ ChunkLds<VT, K> lds;
+    __shared__ ChunkLds<VT, K, NP> lds;
     for (int c = c0; c < c1; ++c)
-        chunk_pass<VT, K, REC, COH>(chunk[c], rowptr, col, val, x, y, q, yq2, rec, lds);
+        chunk_pass<VT, K, REC, COH, NP>(chunk[c], rowptr, col, val, x, y, q, yq2, rec, lds);
 }
 
-// Baseline SpMV: one workgroup per chunk.
+// Baseline SpMV: one workgroup per chunk (chunks of spmv_chunk_nnz(k)).
 template <typename VT, int K, bool REC>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(const int4 *__restrict__ chunk,
                                                       const int32_t *__restrict__ rowptr,
@@ -220,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(const int4 *__restrict__ c
                                                       const VT *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y, int q,
                                                       const double *__restrict__ yq2, RecArgs rec) {
-    chunks_body<VT, K, REC, false>(blockIdx.x, blockIdx.x + 1, chunk, rowptr, col, val, x, y, q, yq2, rec);
+    chunks_body<VT, K, REC, false, spmv_products_per_thread(K)>(blockIdx.x, blockIdx.x + 1, chunk, rowptr, col, val, x,
+                                                                 y, q, yq2, rec);
 }
 
 // Bulk-synchronous level-blocked MPK: one launch computes a list of Lp
@@ -251,7 +255,8 @@ __global__ __launch_bounds__(kBlock) void segment_kernel(SegList L, const int4 *
     const double *x = q == 1 ? X : Y + (int64_t)(q - 2) * NK;
     double *y = Y + (int64_t)(q - 1) * NK;
     RecArgs none{};
-    chunks_body<VT, K, false, false>(c, c + 1, chunk, rowptr, col, val, x, y, q, nullptr, none);
+    chunks_body<VT, K, false, false, mpk_products_per_thread(K)>(c, c + 1, chunk, rowptr, col, val, x, y, q, nullptr,
+                                                                  none);
 }
 
 struct MpkArgs {
@@ -368,7 +373,7 @@ __device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
 }
 
 template <typename VT, int K, bool REC>
-__global__ __launch_bounds__(kBlock, 4) void mpk_persistent(MpkArgs a, RecArgs rec) {
+__global__ __launch_bounds__(kBlock, K == 1 ? 3 : 4) void mpk_persistent(MpkArgs a, RecArgs rec) {
     // The tickets form `nstreams` streams (1, or 8 XCD slices); workgroup b
     // serves stream b % nstreams.  Inside a stream the tickets are dealt over
     // S counters: sub-stripe s holds the stream's tickets s, s + S, ...;
@@ -383,7 +388,8 @@ __global__ __launch_bounds__(kBlock, 4) void mpk_persistent(MpkArgs a, RecArgs r
     __shared__ uint32_t s_epoch;
     __shared__ int s_next[2];
     __shared__ int4 s_rec[2][2];  // the current and the next ticket record
-    __shared__ ChunkLds<VT, K> lds;
+    constexpr int NP = mpk_products_per_thread(K);
+    __shared__ ChunkLds<VT, K, NP> lds;
     const int nS = a.nstreams;
     const int stream = blockIdx.x % nS;
     const int in_stream = (gridDim.x - stream + nS - 1) / nS;
@@ -452,9 +458,9 @@ __global__ __launch_bounds__(kBlock, 4) void mpk_persistent(MpkArgs a, RecArgs r
         // the polling overlap.  The barriers around the poll order only LDS
         // (s_ok) and leave those loads in flight.  For k >= 4 the registers
         // held across the wait cost more occupancy than the overlap gains.
-        const bool pre = K <= 2 && plain_chunk<K>(d0);
-        ChunkRegs<VT, K> g;
-        if (pre) chunk_load<VT, K>(d0, a.rowptr, a.col, val, g);
+        const bool pre = K <= 2 && plain_chunk<K, NP>(d0);
+        ChunkRegs<VT, K, NP> g;
+        if (pre) chunk_load<VT, K, NP>(d0, a.rowptr, a.col, val, g);
         if (q > 1) {
             if (threadIdx.x == 0) s_ok = 1;
             lds_barrier();
@@ -470,25 +476,25 @@ __global__ __launch_bounds__(kBlock, 4) void mpk_persistent(MpkArgs a, RecArgs r
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
         if constexpr (K <= 2) {
             if (pre)
-                chunk_finish<VT, K, REC, true>(d0, g, xin, yout, q, yq2, rec, lds);
+                chunk_finish<VT, K, REC, true, NP>(d0, g, xin, yout, q, yq2, rec, lds);
             else
-                chunk_pass<VT, K, REC, true>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+                chunk_pass<VT, K, REC, true, NP>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
             // later chunks: each descriptor (a scalar load) is read while the
             // chunk before it runs
             int4 dn = table4(a.chunk, c0 + 1 < c1 ? c0 + 1 : c0);
             for (int c = c0 + 1; c < c1; ++c) {
                 const int4 d = dn;
                 dn = table4(a.chunk, c + 1 < c1 ? c + 1 : c);
-                chunk_pass<VT, K, REC, true>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+                chunk_pass<VT, K, REC, true, NP>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
             }
         } else {
-            chunk_pass<VT, K, REC, true>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            chunk_pass<VT, K, REC, true, NP>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
             // later chunks: each descriptor is read while the chunk before it runs
             int4 dn = table4(a.chunk, c0 + 1 < c1 ? c0 + 1 : c0);
             for (int c = c0 + 1; c < c1; ++c) {
                 const int4 d = dn;
                 dn = table4(a.chunk, c + 1 < c1 ? c + 1 : c);
-                chunk_pass<VT, K, REC, true>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+                chunk_pass<VT, K, REC, true, NP>(d, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
             }
         }
         // The next ticket is taken only now: a workgroup never holds a ticket
@@ -1031,6 +1037,13 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         return cleanup_fail(e, "chunks");
     if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
+    std::vector<int32_t> spmv_rows;
+    append_chunks(h.rowptr, 0, h.n, spmv_chunk_nnz(h.opt.nrhs), kChunkRows, spmv_rows);
+    spmv_rows.push_back((int32_t)h.n);
+    const std::vector<int32_t> spmv_desc = chunk_descriptors(spmv_rows, h.rowptr.data());
+    plan->n_chunks_spmv = (int32_t)(spmv_rows.size() - 1);
+    if ((e = dev_alloc(al, &plan->d_chunk_spmv, std::max<size_t>(spmv_desc.size(), 4), &bytes)) != hipSuccess)
+        return cleanup_fail(e, "chunks");
     struct Cp { void *d; const void *s; size_t b; } cps[] = {
         {plan->d_rowptr, h.rowptr.data(), plan->resident ? 0 : sizeof(int32_t) * (h.n + 1)},
         {plan->d_col, h.col.data(), plan->resident ? 0 : sizeof(int32_t) * h.nnz},
@@ -1044,6 +1057,7 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
         {plan->d_perm, h.perm.data(), sizeof(int32_t) * h.n},
         {plan->d_chunk, desc.data(), sizeof(int32_t) * desc.size()},
         {plan->d_tile_chunk, h.tile_chunk.data(), sizeof(int32_t) * h.tile_chunk.size()},
+        {plan->d_chunk_spmv, spmv_desc.data(), sizeof(int32_t) * spmv_desc.size()},
     };
     for (auto &c : cps)
         if (c.b && (e = hipMemcpy(c.d, c.s, c.b, hipMemcpyHostToDevice)) != hipSuccess)
@@ -1188,7 +1202,7 @@ mpk_status mpk_run_baseline_first(mpk_plan *plan, int32_t powers, const double *
     if (!supported(h.opt.val_dtype, h.opt.nrhs, rec != nullptr))
         return fail(MPK_ERR_UNSUPPORTED, "recurrence needs nrhs <= 2");
     const int K = h.opt.nrhs;
-    const int blocks = (int)(h.chunk_row.size() - 1);
+    const int blocks = plan->n_chunks_spmv;
     const int64_t NK = h.n * K;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     for (int q = 1; q <= powers; ++q) {
@@ -1196,7 +1210,7 @@ mpk_status mpk_run_baseline_first(mpk_plan *plan, int32_t powers, const double *
         double *y = Y + (int64_t)(q - 1) * NK;
         const double *yq2 = q == 1 ? ra.y_prev : (q == 2 ? X : Y + (int64_t)(q - 3) * NK);
         hipError_t e = dispatch_all(h.opt.val_dtype, h.opt.accum_f64, K, rec != nullptr, [&](auto d) {
-            return decltype(d)::spmv(blocks, s, reinterpret_cast<const int4 *>(plan->d_chunk), plan->d_rowptr,
+            return decltype(d)::spmv(blocks, s, reinterpret_cast<const int4 *>(plan->d_chunk_spmv), plan->d_rowptr,
                                      plan->d_col, plan->d_val, x, y,
                                      q, yq2, ra);
         });
@@ -1312,7 +1326,7 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
     std::vector<int32_t> chunks;
-    append_chunks(rp, 0, A->n, chunk_nnz_host(o.nrhs), kChunkRows, chunks);
+    append_chunks(rp, 0, A->n, spmv_chunk_nnz(o.nrhs), kChunkRows, chunks);
     chunks.push_back((int32_t)A->n);
     h->nchunks = (int64_t)chunks.size() - 1;
     const std::vector<int32_t> desc = chunk_descriptors(chunks, rp.data());

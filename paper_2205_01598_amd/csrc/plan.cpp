@@ -39,8 +39,6 @@ int32_t bytes_per_nnz(int32_t dtype) {
     }
 }
 
-int32_t chunk_nnz_host(int32_t k) { return 2048 / k; }
-
 template <typename RP>
 static void append_chunks_t(const RP *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
                             std::vector<int32_t> &out) {
@@ -61,6 +59,39 @@ void append_chunks(const std::vector<int32_t> &rowptr, int64_t r0, int64_t r1, i
 void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
                      std::vector<int32_t> &out) {
     append_chunks_t(rowptr, r0, r1, max_nnz, max_rows, out);
+}
+
+// Row boundaries (r0, ..., r1) of the device tiles of rows [r0, r1), one
+// level group or refined unit.  A tile of at least one kernel chunk (cnz
+// nonzeros) is a run of whole chunks: the rows are cut into chunks as the
+// kernel cuts a tile, and the chunks are shared out equally among
+// ceil(chunks / m) tiles, m = tile_nnz / cnz rounded; no tile then ends in
+// a chunk of a few rows.  Smaller tiles share the nonzeros equally.
+static std::vector<int64_t> tile_bounds(const std::vector<int32_t> &rowptr, int64_t r0, int64_t r1,
+                                        int64_t tile_nnz, int64_t cnz) {
+    std::vector<int64_t> bnd{r0};
+    if (tile_nnz >= cnz) {
+        std::vector<int32_t> ch;
+        append_chunks(rowptr, r0, r1, cnz, kChunkRows, ch);
+        const int64_t C = (int64_t)ch.size();
+        const int64_t m = std::max<int64_t>((tile_nnz + cnz / 2) / cnz, 1);
+        const int64_t nt = std::max<int64_t>(1, (C + m - 1) / m);
+        for (int64_t t = 1; t < nt; ++t) bnd.push_back(ch[(size_t)(C * t / nt)]);
+    } else {
+        // equal-nonzero split into ceil(gnz / tile_nnz) tiles
+        const int64_t gnz = rowptr[r1] - rowptr[r0];
+        int64_t nt = std::max<int64_t>(1, (gnz + tile_nnz - 1) / tile_nnz);
+        nt = std::min<int64_t>(nt, r1 - r0);
+        for (int64_t t = 1; t < nt; ++t) {
+            const int64_t target = rowptr[r0] + (gnz * t) / nt;
+            const int64_t lo = bnd.back() + 1, hi = r1 - (nt - t);
+            const int64_t a =
+                std::lower_bound(rowptr.begin() + lo, rowptr.begin() + hi + 1, (int32_t)target) - rowptr.begin();
+            bnd.push_back(std::min<int64_t>(std::max<int64_t>(a, lo), hi));
+        }
+    }
+    bnd.push_back(r1);
+    return bnd;
 }
 
 mpk_status validate_csr(const mpk_csr *A) {
@@ -519,18 +550,7 @@ mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &
     for (int64_t u = 0; u < U; ++u) {
         hp.group_tile.push_back((int32_t)hp.tile_group.size());
         const int64_t r0 = hp.unit_ptr[u], r1 = hp.unit_ptr[u + 1];
-        const int64_t gnz = hp.rowptr[r1] - hp.rowptr[r0];
-        int64_t nt = std::max<int64_t>(1, (gnz + tile_nnz - 1) / tile_nnz);
-        nt = std::min<int64_t>(nt, r1 - r0);
-        std::vector<int64_t> bnd{r0};
-        for (int64_t t = 1; t < nt; ++t) {
-            const int64_t target = hp.rowptr[r0] + (gnz * t) / nt;
-            const int64_t lo = bnd.back() + 1, hi = r1 - (nt - t);
-            const int64_t a = std::lower_bound(hp.rowptr.begin() + lo, hp.rowptr.begin() + hi + 1, (int32_t)target) -
-                              hp.rowptr.begin();
-            bnd.push_back(std::min<int64_t>(std::max<int64_t>(a, lo), hi));
-        }
-        bnd.push_back(r1);
+        const std::vector<int64_t> bnd = tile_bounds(hp.rowptr, r0, r1, tile_nnz, mpk_chunk_nnz(opt.nrhs));
         for (size_t t = 0; t + 1 < bnd.size(); ++t)
             for (int64_t r = bnd[t]; r < bnd[t + 1]; r += max_tile_rows) {
                 hp.tile_row.push_back((int32_t)r);
@@ -596,7 +616,7 @@ mpk_status build_recursive_schedule(HostPlan &hp, int32_t p, const mpk_options &
     // kernel chunks inside every tile
     hp.chunk_row.clear();
     hp.tile_chunk.assign(T + 1, 0);
-    const int64_t cnz = chunk_nnz_host(opt.nrhs);
+    const int64_t cnz = mpk_chunk_nnz(opt.nrhs);
     for (int64_t t = 0; t < T; ++t) {
         hp.tile_chunk[t] = (int32_t)hp.chunk_row.size();
         append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, kChunkRows, hp.chunk_row);
@@ -710,22 +730,9 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         hp.group_tile.clear();
         for (int64_t gi = 0; gi < G; ++gi) {
             hp.group_tile.push_back((int32_t)hp.tile_group.size());
-            int64_t r0 = hp.level_ptr[hp.group_ptr[gi]];
-            int64_t r1 = hp.level_ptr[hp.group_ptr[gi + 1]];
-            int64_t gnz = hp.rowptr[r1] - hp.rowptr[r0];
-            // equal-nonzero split of the group into ceil(gnz / tile_nnz) tiles
-            int64_t nt = std::max<int64_t>(1, (gnz + tile_nnz - 1) / tile_nnz);
-            nt = std::min<int64_t>(nt, r1 - r0);
-            std::vector<int64_t> bnd;
-            bnd.push_back(r0);
-            for (int64_t t = 1; t < nt; ++t) {
-                int64_t target = hp.rowptr[r0] + (gnz * t) / nt;
-                int64_t lo = bnd.back() + 1, hi = r1 - (nt - t);
-                int64_t a = std::lower_bound(hp.rowptr.begin() + lo, hp.rowptr.begin() + hi + 1,
-                                             (int32_t)target) - hp.rowptr.begin();
-                bnd.push_back(std::min<int64_t>(std::max<int64_t>(a, lo), hi));
-            }
-            bnd.push_back(r1);
+            const int64_t r0 = hp.level_ptr[hp.group_ptr[gi]];
+            const int64_t r1 = hp.level_ptr[hp.group_ptr[gi + 1]];
+            const std::vector<int64_t> bnd = tile_bounds(hp.rowptr, r0, r1, tile_nnz, mpk_chunk_nnz(opt.nrhs));
             for (size_t t = 0; t + 1 < bnd.size(); ++t) {
                 for (int64_t r = bnd[t]; r < bnd[t + 1]; r += max_tile_rows) {
                     hp.tile_row.push_back((int32_t)r);
@@ -846,7 +853,7 @@ mpk_status build_schedule(HostPlan &hp, int32_t p, uint64_t cache_bytes, const m
         // kernel chunks inside every tile
         hp.chunk_row.clear();
         hp.tile_chunk.assign(T + 1, 0);
-        const int64_t cnz = chunk_nnz_host(opt.nrhs);
+        const int64_t cnz = mpk_chunk_nnz(opt.nrhs);
         for (int64_t t = 0; t < T; ++t) {
             hp.tile_chunk[t] = (int32_t)hp.chunk_row.size();
             append_chunks(hp.rowptr, hp.tile_row[t], hp.tile_row[t + 1], cnz, kChunkRows, hp.chunk_row);

@@ -336,15 +336,17 @@ def test_run_argument_errors():
 
 @pytest.mark.parametrize("k", [1, 2, 4, 32])
 def test_long_rows_and_chunk_edges(k):
-    # rows longer than a chunk (one dense row and power-law rows) take the
-    # strided path; chunk boundaries fall at every position
+    # rows longer than a chunk (one dense row, longer than the 4096-entry MPK
+    # chunk of k = 1, and power-law rows) take the strided path; chunk
+    # boundaries fall at every position
     rng = np.random.default_rng(k)
-    A = W.zipf_rows(4000, 1.5, seed=k)
-    dense = np.arange(4000, dtype=np.int32)
-    rowptr = np.concatenate([[0], A.rowptr[1:] - A.rowptr[1] + 4000]).astype(np.int64)
+    n = 5000
+    A = W.zipf_rows(n, 1.5, seed=k)
+    dense = np.arange(n, dtype=np.int32)
+    rowptr = np.concatenate([[0], A.rowptr[1:] - A.rowptr[1] + n]).astype(np.int64)
     col = np.concatenate([dense, A.col[A.rowptr[1]:]]).astype(np.int32)
-    val = np.concatenate([rng.uniform(-1, 1, 4000) / 4000, A.val[A.rowptr[1]:]])
-    B = W.CSR(4000, rowptr, col, val)
+    val = np.concatenate([rng.uniform(-1, 1, n) / n, A.val[A.rowptr[1]:]])
+    B = W.CSR(n, rowptr, col, val)
     X = W.gaussian_block(B.n, k, seed=k) if k > 1 else W.uniform_vector(B.n, seed=k)
     ref = O.spmv_powers(B, X, 4)
     for tile in (500, 5000):

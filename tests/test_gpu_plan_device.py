@@ -122,12 +122,12 @@ def test_device_resident_plan_equals_host_plan(name, A, root_mode):
     yr = _run_bits(res, x, p, dev)
     assert np.array_equal(yr, _run_bits(host, x, p, dev))
     # and the oracle on the renumbered matrix: bit for bit, except where a
-    # row is longer than one kernel chunk (2048 entries at k = 1) and is
+    # row is longer than one MPK chunk (4096 entries at k = 1) and is
     # reduced by a tree across the workgroup
     perm = res.arrays()[0].astype(np.int64)
     rpo, co, vo = O.permute_symmetric(A, perm)
     ref = O.spmv_powers(W.CSR(A.n, rpo, co, vo), np.ascontiguousarray(x[perm]), p)
-    if np.diff(A.rowptr).max(initial=0) <= 2048:
+    if np.diff(A.rowptr).max(initial=0) <= 4096:
         assert np.array_equal(yr, ref.view(np.int64))
     else:
         got = yr.view(np.float64)
