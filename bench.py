@@ -213,15 +213,27 @@ def plan_device_only(args):
     A, _ = W.stencil_27pt_random(args.n, seed=args.seed)
     dA = [torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (A.rowptr, A.col, A.val)]
     secs = []
+    pl = None
     for _ in range(2):
+        del pl  # the previous plan is freed before the clock starts
         torch.cuda.synchronize()
         t0 = time.time()
         pl = Plan.from_device(*dA, args.p, 256 << 20, root_mode=1)
         torch.cuda.synchronize()
         secs.append(time.time() - t0)
     inf = pl.info()
+    del pl
+    # a third plan with the upload (schedule tables to the device) timed apart
+    torch.cuda.synchronize()
+    t0 = time.time()
+    pl3 = Plan.from_device(*dA, args.p, 256 << 20, root_mode=1, upload=False)
+    t1 = time.time()
+    pl3.upload()
+    torch.cuda.synchronize()
+    t2 = time.time()
     print(json.dumps({"plan_seconds": [round(v, 4) for v in secs], "levels": inf["n_levels"],
-                      "phase_seconds": [round(v, 4) for v in inf["phase_seconds"]]}), flush=True)
+                      "phase_seconds": [round(v, 4) for v in inf["phase_seconds"]],
+                      "create_seconds": round(t1 - t0, 4), "upload_seconds": round(t2 - t1, 4)}), flush=True)
 
 
 def only_config(args):
@@ -633,7 +645,9 @@ def main():
     # a plan ready to run); its run equals the host plan's bit for bit
     dA = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (A.rowptr, A.col, A.val)]
     resident = {}
+    pres = None
     for _ in range(2):
+        del pres  # the previous plan is freed before the clock starts
         torch.cuda.synchronize()
         t0 = time.time()
         pres = Plan.from_device(*dA, p, 256 << 20, root_mode=1)

@@ -39,15 +39,20 @@ int32_t bytes_per_nnz(int32_t dtype) {
     }
 }
 
+// Greedy chunks: a chunk starting at row r takes the most rows, at least
+// one and at most max_rows, whose entries fit in max_nnz.  The end row is
+// found by a binary search of the row pointers (non-decreasing).
 template <typename RP>
 static void append_chunks_t(const RP *rowptr, int64_t r0, int64_t r1, int64_t max_nnz, int64_t max_rows,
                             std::vector<int32_t> &out) {
     int64_t r = r0;
     while (r < r1) {
         out.push_back((int32_t)r);
-        int64_t e = r + 1;
-        while (e < r1 && e - r < max_rows && (int64_t)(rowptr[e + 1] - rowptr[r]) <= max_nnz) ++e;
-        r = e;
+        const int64_t lim = std::min<int64_t>(r1, r + max_rows);
+        const int64_t target = (int64_t)rowptr[r] + max_nnz;
+        const RP *e = std::upper_bound(rowptr + r + 1, rowptr + lim + 1, target,
+                                       [](int64_t t, RP v) { return t < (int64_t)v; });
+        r = std::max<int64_t>(r + 1, (e - rowptr) - 1);
     }
 }
 
@@ -1026,8 +1031,12 @@ mpk_status build_resident_plan(const mpk_csr *A, int32_t p, uint64_t cache_bytes
     hp.dev_rowptr = M->rowptr;
     hp.dev_col = M->col;
     try {
-        hp.iperm.assign(hp.n, 0);
-        for (int64_t i = 0; i < hp.n; ++i) hp.iperm[hp.perm[i]] = (int32_t)i;
+        hp.iperm.resize(hp.n);
+        int32_t *ip = hp.iperm.data();
+        const int32_t *pm = hp.perm.data();
+        const int64_t n = hp.n;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) ip[pm[i]] = (int32_t)i;  // perm is a permutation: distinct targets
         level_counts(hp);
     } catch (const std::bad_alloc &) {
         return fail(MPK_ERR_OOM, "host allocation failed while planning");

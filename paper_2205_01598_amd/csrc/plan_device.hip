@@ -14,14 +14,14 @@
 //   count        a workgroup scan of those counts gives each vertex's offset
 //                inside its chunk of 256 frontier positions;
 //   scan_blocks  one workgroup scans the chunk totals (the next frontier's
-//                size);
+//                size), records the level and writes the next frontier;
 //   scatter      every frontier vertex writes the neighbours it owns, in
 //                row order, at b + its offset, and marks them seen.
-// The frontier bounds live in device memory (Frontier), and a one-thread
-// kernel (advance) records the level and moves the frontier on, so the host
-// enqueues levels in batches (1, 2, 4, ... up to 32) and reads the state back
-// once per batch; levels enqueued after the component is exhausted do
-// nothing.  An empty frontier with vertices left starts a new component at
+// The frontier bounds live in device memory (Frontier), in two copies that
+// alternate from level to level: the kernels of a level read the current
+// one and scan_blocks writes the next, so the host enqueues levels in
+// batches (1, 2, 4, ... up to 32) and reads the state back once per batch;
+// levels enqueued after the component is exhausted do nothing.  An empty frontier with vertices left starts a new component at
 // the smallest unnumbered index (a reduction), as a new level.  owner[v] is
 // INT32_MAX for an unnumbered vertex and a position below the current
 // frontier otherwise; a bitmap of numbered vertices lets the kernels skip
@@ -64,8 +64,9 @@ __global__ void set_root(int32_t *order, int32_t *owner, uint32_t *seen, int64_t
 // the neighbours numbered in earlier levels, about two thirds of them.
 __device__ __forceinline__ bool is_seen(const uint32_t *seen, int32_t v) { return (seen[v >> 5] >> (v & 31)) & 1u; }
 
-// Frontier of the level expansion: order[a, b); next = size of the next
-// frontier (set by scan_blocks); lv = levels recorded in the level-end array.
+// Frontier of the level expansion: order[a, b); next = size of this
+// frontier's successor (set with it by scan_blocks); lv = levels recorded in
+// the level-end array.
 struct Frontier {
     int64_t a, b, next, lv;
 };
@@ -156,9 +157,10 @@ __global__ void count(const int32_t *__restrict__ cnt, const Frontier *__restric
     }
 }
 
-// one workgroup: exclusive scan of the chunk totals in place, grand total to
-// fr->next
-__global__ void scan_blocks(int32_t *blocksum, Frontier *fr) {
+// one workgroup: exclusive scan of the chunk totals in place; then a
+// non-empty frontier fr becomes a level (its end recorded) and the frontier
+// after it goes to nx (an empty one is copied: nothing is left to expand)
+__global__ void scan_blocks(int32_t *blocksum, const Frontier *fr, Frontier *nx, int32_t *level_end) {
     __shared__ int32_t s[kThreads];
     const int64_t nb = (fr->b - fr->a + kThreads - 1) / kThreads;
     int32_t carry = 0;
@@ -178,7 +180,15 @@ __global__ void scan_blocks(int32_t *blocksum, Frontier *fr) {
         __syncthreads();
         carry += step;
     }
-    if (threadIdx.x == 0) fr->next = carry;
+    if (threadIdx.x == 0) {
+        const int64_t a = fr->a, b = fr->b, lv = fr->lv;
+        if (a >= b) {
+            *nx = Frontier{a, b, 0, lv};
+        } else {
+            level_end[lv] = (int32_t)b;
+            *nx = Frontier{b, b + carry, carry, lv + 1};
+        }
+    }
 }
 
 // Each frontier vertex writes the neighbours it owns, in row order, and
@@ -213,17 +223,6 @@ __global__ void scatter(const int64_t *__restrict__ ptr, const int32_t *__restri
             o += __popc(m);
         }
     }
-}
-
-// one thread: a non-empty frontier becomes a level (its end recorded) and
-// the next frontier follows it
-__global__ void advance(Frontier *fr, int32_t *level_end) {
-    const int64_t a = fr->a, b = fr->b;
-    if (a >= b) return;
-    level_end[fr->lv] = (int32_t)b;
-    fr->lv = fr->lv + 1;
-    fr->a = b;
-    fr->b = b + fr->next;
 }
 
 // smallest index v with owner[v] == INT32_MAX (n if none)
@@ -291,6 +290,7 @@ inline unsigned grid_for(int64_t items) { return (unsigned)((items + kThreads - 
 // position after the component in *end.
 mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> &lptr, int64_t *end) {
     Frontier h{start, start + 1, 0, 0};
+    int cur = 0;  // which of the two frontier copies is current
     LV_TRY(hipMemcpy(g.front, &h, sizeof(h), hipMemcpyHostToDevice));
     // grids sized for the widest possible frontier, capped; slots beyond the
     // current frontier exit at once
@@ -298,18 +298,19 @@ mpk_status expand_component(DeviceGraph &g, int64_t start, std::vector<int32_t> 
     const unsigned ne = std::max(1u, (unsigned)std::min<int64_t>((g.n * kLanes + kThreads - 1) / kThreads, 2048));
     for (int batch = 1;; batch = std::min(2 * batch, 32)) {
         for (int i = 0; i < batch; ++i) {
-            hipLaunchKernelGGL(claim, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.front, g.owner,
-                               g.seen);
-            hipLaunchKernelGGL(count_owned, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
+            const Frontier *fr = g.front + cur;
+            hipLaunchKernelGGL(claim, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, fr, g.owner, g.seen);
+            hipLaunchKernelGGL(count_owned, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, fr,
                                g.cnt, g.seen);
-            hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.cnt, g.front, g.local, g.blocksum);
-            hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, g.front);
-            hipLaunchKernelGGL(scatter, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, g.front,
-                               g.local, g.blocksum, g.seen);
-            hipLaunchKernelGGL(advance, dim3(1), dim3(1), 0, 0, g.front, g.level_end);
+            hipLaunchKernelGGL(count, dim3(nb), dim3(kThreads), 0, 0, g.cnt, fr, g.local, g.blocksum);
+            hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(kThreads), 0, 0, g.blocksum, fr, g.front + (cur ^ 1),
+                               g.level_end);
+            hipLaunchKernelGGL(scatter, dim3(ne), dim3(kThreads), 0, 0, g.ptr, g.adj, g.order, g.owner, fr, g.local,
+                               g.blocksum, g.seen);
+            cur ^= 1;
         }
         LV_TRY(hipGetLastError());
-        LV_TRY(hipMemcpy(&h, g.front, sizeof(h), hipMemcpyDeviceToHost));
+        LV_TRY(hipMemcpy(&h, g.front + cur, sizeof(h), hipMemcpyDeviceToHost));
         if (h.b > g.n || h.a > h.b || h.lv > g.n) return fail(MPK_ERR_HIP, "device levels: inconsistent frontier");
         if (h.a == h.b) break;
     }
@@ -355,7 +356,7 @@ mpk_status alloc_bfs(DeviceGraph &g) {
     LV_TRY(dalloc(g, &g.bk_seen, (n + 31) / 32));
     LV_TRY(dalloc(g, &g.bk_order, n));
     LV_TRY(dalloc(g, &g.bk_owner, n));
-    LV_TRY(dalloc(g, &g.front, 1));
+    LV_TRY(dalloc(g, &g.front, 2));
     return MPK_OK;
 }
 
