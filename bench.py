@@ -674,7 +674,8 @@ def main():
     log(f"baselines (ms): {base}")
 
     # ---- MPK configuration: small sweep on the same levels ------------------------
-    cands = [dict(cache_mb=256, skew=2, tile_nnz=8192), dict(cache_mb=256, skew=2, tile_nnz=6144),
+    # tiles of 1, 2 and 3 whole 4096-nonzero chunks
+    cands = [dict(cache_mb=256, skew=2, tile_nnz=8192), dict(cache_mb=256, skew=2, tile_nnz=12288),
              dict(cache_mb=256, skew=2, tile_nnz=4096), dict(cache_mb=512, skew=2, tile_nnz=8192)]
     if args.quick:
         cands = cands[:1]
