@@ -300,3 +300,44 @@ def test_abi_struct_sizes():
     assert o.safety_factor == 0.5 and o.nrhs == 1 and o.val_dtype == 0
     assert _lib.lib().mpk_status_string(-5).decode() == "device dependency wait timed out"
     assert _lib.lib().mpk_version().decode().startswith("mpk-gfx950")
+
+
+def _greedy_chunks(rp, r0, r1, max_nnz, max_rows=1024):
+    """Chunk start rows of rows [r0, r1): each chunk takes the most rows (at
+    least one, at most max_rows) whose entries fit in max_nnz."""
+    out, r = [], r0
+    while r < r1:
+        out.append(r)
+        e = r + 1
+        while e < r1 and e - r < max_rows and rp[e + 1] - rp[r] <= max_nnz:
+            e += 1
+        r = e
+    return out
+
+
+@pytest.mark.parametrize("k,tile", [(1, 8192), (1, 12288), (1, 6000), (2, 4096), (4, 4096), (1, 1000)])
+def test_tiles_are_runs_of_whole_chunks(k, tile):
+    # A tile of at least one kernel chunk (4096 nonzeros at k = 1, 2048/k
+    # otherwise, include/mpk.h) is a run of whole chunks: its group's rows
+    # cut greedily into chunks, round(tile / chunk) chunks per tile, shared
+    # out equally.  Smaller tiles split the nonzeros equally.
+    A, _ = W.stencil_27pt_random(20, seed=3)
+    pl = Plan(A, 4, 1 << 20, upload=False, root_mode=1, nrhs=k, tile_nnz=tile)
+    _, lp, gp, _ = pl.arrays()
+    rp = pl.matrix()[0]
+    tr = pl.tiles()[0]
+    cnz = 4096 if k == 1 else 2048 // k
+    group_rows = lp[gp]
+    n_chunks = 0
+    for g in range(len(gp) - 1):
+        r0, r1 = int(group_rows[g]), int(group_rows[g + 1])
+        bounds = [int(v) for v in tr if r0 <= v < r1]
+        assert bounds[0] == r0
+        if tile >= cnz:
+            ch = _greedy_chunks(rp, r0, r1, cnz)
+            m = max(1, (tile + cnz // 2) // cnz)
+            nt = max(1, -(-len(ch) // m))
+            assert bounds == [ch[len(ch) * t // nt] for t in range(nt)]
+        for a, b in zip(bounds, bounds[1:] + [r1]):
+            n_chunks += len(_greedy_chunks(rp, a, b, cnz))
+    assert pl.info()["n_chunks"] == n_chunks
