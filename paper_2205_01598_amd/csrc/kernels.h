@@ -241,12 +241,13 @@ __device__ __forceinline__ bool plain_chunk(const int4 d) {
 }
 
 // Phase 1, first half, of a plain chunk d = (r0, r1, j0, j1): the row
-// pointers rowptr[r0 .. r1] (uniform guards) and the chunk's col/val entries.
-// Every load is unconditional (slots past the chunk re-read its last entry,
-// whose product phase 2 never reads), so they are all in flight together.
-// Nothing here depends on vector data: a caller may issue these loads
-// before it has waited for the vector the chunk multiplies.
-template <typename VT, int K, int NP>
+// pointers rowptr[r0 .. r1] (uniform guards) and the chunk's col entries,
+// with its val entries unless VALS is false.  Every load is unconditional
+// (slots past the chunk re-read its last entry, whose product phase 2 never
+// reads), so they are all in flight together.  Nothing here depends on
+// vector data: a caller may issue these loads before it has waited for the
+// vector the chunk multiplies.
+template <typename VT, int K, int NP, bool VALS = true>
 __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restrict__ rowptr,
                                            const int32_t *__restrict__ col, const VT *__restrict__ val,
                                            ChunkRegs<VT, K, NP> &g) {
@@ -261,6 +262,20 @@ __device__ __forceinline__ void chunk_load(const int4 d, const int32_t *__restri
         const int pidx = tid + m * kBlock;
         const int jc = min(d.z + pidx / K, d.w - 1);
         g.cj[m] = col[jc];
+        if constexpr (VALS) g.a[m] = (AT)load_value(val, jc);
+    }
+}
+
+// The values of a plain chunk whose row pointers and columns chunk_load
+// (VALS = false) has already loaded.
+template <typename VT, int K, int NP>
+__device__ __forceinline__ void chunk_load_vals(const int4 d, const VT *__restrict__ val, ChunkRegs<VT, K, NP> &g) {
+    using AT = typename AccumType<VT>::T;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int pidx = tid + m * kBlock;
+        const int jc = min(d.z + pidx / K, d.w - 1);
         g.a[m] = (AT)load_value(val, jc);
     }
 }

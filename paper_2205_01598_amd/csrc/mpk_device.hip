@@ -25,6 +25,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -372,8 +373,17 @@ __device__ __forceinline__ uint32_t *stripe_counter(const MpkArgs &a, int s) {
     return a.ctrl + kStripeBase + s * kStripeStride;
 }
 
+// Before its dependency wait a tile loads its first chunk's row pointers
+// and columns, and with FP64 values (k <= 2) the values too; FP32 and BF16
+// values are loaded after the wait, together with the gathers, which keeps
+// the registers held across the wait low enough for 4 workgroups per CU at
+// k = 1 (FP64 holds them all and runs at 3 per CU, the faster of the two for
+// each value type).
+template <typename VT>
+constexpr bool kPreloadValues = std::is_same<VT, double>::value;
+
 template <typename VT, int K, bool REC>
-__global__ __launch_bounds__(kBlock, K == 1 ? 3 : 4) void mpk_persistent(MpkArgs a, RecArgs rec) {
+__global__ __launch_bounds__(kBlock, K == 1 && kPreloadValues<VT> ? 3 : 4) void mpk_persistent(MpkArgs a, RecArgs rec) {
     // The tickets form `nstreams` streams (1, or 8 XCD slices); workgroup b
     // serves stream b % nstreams.  Inside a stream the tickets are dealt over
     // S counters: sub-stripe s holds the stream's tickets s, s + S, ...;
@@ -460,7 +470,7 @@ __global__ __launch_bounds__(kBlock, K == 1 ? 3 : 4) void mpk_persistent(MpkArgs
         // held across the wait cost more occupancy than the overlap gains.
         const bool pre = K <= 2 && plain_chunk<K, NP>(d0);
         ChunkRegs<VT, K, NP> g;
-        if (pre) chunk_load<VT, K, NP>(d0, a.rowptr, a.col, val, g);
+        if (pre) chunk_load<VT, K, NP, kPreloadValues<VT>>(d0, a.rowptr, a.col, val, g);
         if (q > 1) {
             if (threadIdx.x == 0) s_ok = 1;
             lds_barrier();
@@ -475,10 +485,12 @@ __global__ __launch_bounds__(kBlock, K == 1 ? 3 : 4) void mpk_persistent(MpkArgs
         double *yout = a.Y + (int64_t)(q - 1) * NK;
         const double *yq2 = (q == 1) ? rec.y_prev : (q == 2 ? a.X : a.Y + (int64_t)(q - 3) * NK);
         if constexpr (K <= 2) {
-            if (pre)
+            if (pre) {
+                if constexpr (!kPreloadValues<VT>) chunk_load_vals<VT, K, NP>(d0, val, g);
                 chunk_finish<VT, K, REC, true, NP>(d0, g, xin, yout, q, yq2, rec, lds);
-            else
+            } else {
                 chunk_pass<VT, K, REC, true, NP>(d0, a.rowptr, a.col, val, xin, yout, q, yq2, rec, lds);
+            }
             // later chunks: each descriptor (a scalar load) is read while the
             // chunk before it runs
             int4 dn = table4(a.chunk, c0 + 1 < c1 ? c0 + 1 : c0);
