@@ -135,7 +135,8 @@ typedef struct mpk_plan_info {
     int64_t violating_groups; /* groups that break Eq. (5) (single bulky levels) */
     uint64_t device_bytes;    /* device memory held after mpk_plan_upload */
     int32_t workgroups;       /* grid size mpk_run will launch */
-    int32_t n_chunks;         /* kernel work units (<= chunk_nnz(k) nonzeros each) */
+    int32_t n_chunks;         /* MPK kernel work units inside the tiles (<= 4096
+                                 nonzeros at nrhs = 1, 2048/nrhs otherwise) */
     int32_t tile_nnz;
     int32_t val_dtype;
     double plan_seconds;      /* host time spent in mpk_plan_create */
