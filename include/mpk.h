@@ -83,8 +83,8 @@ typedef struct mpk_options {
     int32_t workgroups;       /* persistent-kernel grid size; 0 = automatic */
     int32_t tile_nnz;         /* target nonzeros per device tile; 0 = 8192.  At or
                                  above one kernel chunk (4096 nonzeros at nrhs = 1,
-                                 2048/nrhs otherwise) a tile is a run of
-                                 round(tile_nnz / chunk) whole chunks */
+                                 1024 at nrhs = 2, 4096/nrhs for nrhs >= 4) a tile
+                                 is a run of round(tile_nnz / chunk) whole chunks */
     int32_t reserved0;        /* must be 0 */
     int64_t watchdog_spins;   /* dependency-wait polls before MPK_ERR_TIMEOUT; 0 = default */
     int32_t budget_vectors;   /* 1: Eq. (5) also counts the k vector entries per row
@@ -136,7 +136,8 @@ typedef struct mpk_plan_info {
     uint64_t device_bytes;    /* device memory held after mpk_plan_upload */
     int32_t workgroups;       /* grid size mpk_run will launch */
     int32_t n_chunks;         /* MPK kernel work units inside the tiles (<= 4096
-                                 nonzeros at nrhs = 1, 2048/nrhs otherwise) */
+                                 nonzeros at nrhs = 1, 1024 at nrhs = 2,
+                                 4096/nrhs for nrhs >= 4) */
     int32_t tile_nnz;
     int32_t val_dtype;
     double plan_seconds;      /* host time spent in mpk_plan_create */

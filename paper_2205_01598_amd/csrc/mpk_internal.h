@@ -123,13 +123,13 @@ void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_
 
 // Products each of a chunk's 256 threads forms, for k right-hand sides.  The
 // persistent MPK kernel (and the bulk-synchronous kernels, which run on the
-// same tile chunks) takes 16 at k = 1: more loads in flight per wavefront at
-// 3 workgroups per CU.  The baseline SpMV, one workgroup per chunk, is
-// fastest at 12.  Both take 8 for k >= 2, where the epilogue needs the
-// registers.  Host (chunk cutting) and device (chunk kernel) use the same
-// values.
-constexpr int32_t mpk_products_per_thread(int32_t k) { return k == 1 ? 16 : 8; }
-constexpr int32_t spmv_products_per_thread(int32_t k) { return k == 1 ? 12 : 8; }
+// same tile chunks) takes 16 at k = 1 (more loads in flight per wavefront
+// at 3 workgroups per CU); the baseline SpMV, one workgroup per chunk, is
+// fastest at 12 there.  At k = 2 both take 8: the recurrence epilogue needs
+// the registers.  For k >= 4 both take 16.  Host (chunk cutting) and device
+// (chunk kernel) use the same values.
+constexpr int32_t mpk_products_per_thread(int32_t k) { return k == 2 ? 8 : 16; }
+constexpr int32_t spmv_products_per_thread(int32_t k) { return k == 1 ? 12 : k == 2 ? 8 : 16; }
 // Nonzeros per kernel chunk for k right-hand sides.
 constexpr int32_t mpk_chunk_nnz(int32_t k) { return 256 * mpk_products_per_thread(k) / k; }
 constexpr int32_t spmv_chunk_nnz(int32_t k) { return 256 * spmv_products_per_thread(k) / k; }

@@ -14,9 +14,10 @@ equal bit for bit:
 * FP32 / BF16 storage with FP64 arithmetic (accum_f64): oracle.spmv_powers on
   the rounded values of P A P^T.
 
-Rows longer than one chunk (MPK: 4096 stored entries at k = 1, 2048/k for
-k >= 2; baseline SpMV: 3072 at k = 1) are reduced by a tree and are not
-covered here; none of these matrices has one.  The recurrence
+Rows longer than one chunk (MPK: 4096 stored entries at k = 1, 1024 at
+k = 2, 4096/k for k >= 4; baseline SpMV: 3072 at k = 1, otherwise the same)
+are reduced by a tree and are not covered here; none of these matrices has
+one.  The recurrence
 epilogue (Chebyshev) keeps its 1e-12 bar in the other tests."""
 import numpy as np
 import pytest

@@ -317,16 +317,16 @@ def _greedy_chunks(rp, r0, r1, max_nnz, max_rows=1024):
 
 @pytest.mark.parametrize("k,tile", [(1, 8192), (1, 12288), (1, 6000), (2, 4096), (4, 4096), (1, 1000)])
 def test_tiles_are_runs_of_whole_chunks(k, tile):
-    # A tile of at least one kernel chunk (4096 nonzeros at k = 1, 2048/k
-    # otherwise, include/mpk.h) is a run of whole chunks: its group's rows
-    # cut greedily into chunks, round(tile / chunk) chunks per tile, shared
-    # out equally.  Smaller tiles split the nonzeros equally.
+    # A tile of at least one kernel chunk (4096 nonzeros at k = 1, 1024 at
+    # k = 2, 4096/k for k >= 4, include/mpk.h) is a run of whole chunks: its
+    # group's rows cut greedily into chunks, round(tile / chunk) chunks per
+    # tile, shared out equally.  Smaller tiles split the nonzeros equally.
     A, _ = W.stencil_27pt_random(20, seed=3)
     pl = Plan(A, 4, 1 << 20, upload=False, root_mode=1, nrhs=k, tile_nnz=tile)
     _, lp, gp, _ = pl.arrays()
     rp = pl.matrix()[0]
     tr = pl.tiles()[0]
-    cnz = 4096 if k == 1 else 2048 // k
+    cnz = 1024 if k == 2 else 4096 // k
     group_rows = lp[gp]
     n_chunks = 0
     for g in range(len(gp) - 1):
