@@ -109,7 +109,7 @@ static_assert(kBlock == 256, "the chunk lengths of mpk_internal.h assume 256 thr
 // kBlock * NP products (NP * 2 KB of LDS in FP64).  The persistent MPK kernel
 // and the bulk-synchronous kernels run on the plan's tile chunks with
 // NP = mpk_products_per_thread(k), the baseline SpMV on chunks of its own
-// with NP = spmv_products_per_thread(k).
+// with NP = spmv_products_per_thread(k, FP32 products).
 __host__ __device__ constexpr int chunk_nnz(int K, int NP) { return kBlock * NP / K; }
 template <typename VT, int K, int NP>
 struct ChunkLds {

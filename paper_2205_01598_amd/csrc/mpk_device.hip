@@ -216,7 +216,7 @@ __device__ __forceinline__ void chunks_body(int c0, int c1, const int4 *__restri
         chunk_pass<VT, K, REC, COH, NP>(chunk[c], rowptr, col, val, x, y, q, yq2, rec, lds);
 }
 
-// Baseline SpMV: one workgroup per chunk (chunks of spmv_chunk_nnz(k)).
+// Baseline SpMV: one workgroup per chunk (chunks of spmv_chunk_nnz).
 template <typename VT, int K, bool REC>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(const int4 *__restrict__ chunk,
                                                       const int32_t *__restrict__ rowptr,
@@ -224,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(const int4 *__restrict__ c
                                                       const VT *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y, int q,
                                                       const double *__restrict__ yq2, RecArgs rec) {
-    chunks_body<VT, K, REC, false, spmv_products_per_thread(K)>(blockIdx.x, blockIdx.x + 1, chunk, rowptr, col, val, x,
-                                                                 y, q, yq2, rec);
+    constexpr int NP = spmv_products_per_thread(K, std::is_same<typename AccumType<VT>::T, float>::value);
+    chunks_body<VT, K, REC, false, NP>(blockIdx.x, blockIdx.x + 1, chunk, rowptr, col, val, x, y, q, yq2, rec);
 }
 
 // Bulk-synchronous level-blocked MPK: one launch computes a list of Lp
@@ -1050,7 +1050,8 @@ mpk_status mpk_plan_upload(mpk_plan *plan) {
     if ((e = dev_alloc(al, &plan->d_tile_chunk, h.tile_chunk.size(), &bytes)) != hipSuccess)
         return cleanup_fail(e, "chunks");
     std::vector<int32_t> spmv_rows;
-    append_chunks(h.rowptr, 0, h.n, spmv_chunk_nnz(h.opt.nrhs), kChunkRows, spmv_rows);
+    append_chunks(h.rowptr, 0, h.n, spmv_chunk_nnz(h.opt.nrhs, fp32_products(h.opt.val_dtype, h.opt.accum_f64)),
+                  kChunkRows, spmv_rows);
     spmv_rows.push_back((int32_t)h.n);
     const std::vector<int32_t> spmv_desc = chunk_descriptors(spmv_rows, h.rowptr.data());
     plan->n_chunks_spmv = (int32_t)(spmv_rows.size() - 1);
@@ -1338,7 +1339,7 @@ mpk_status spmv_create(const mpk_csr *A, const mpk_options *opt, mpk_spmv **out)
     std::vector<int32_t> rp(A->n + 1);
     for (int64_t i = 0; i <= A->n; ++i) rp[i] = (int32_t)A->rowptr[i];
     std::vector<int32_t> chunks;
-    append_chunks(rp, 0, A->n, spmv_chunk_nnz(o.nrhs), kChunkRows, chunks);
+    append_chunks(rp, 0, A->n, spmv_chunk_nnz(o.nrhs, fp32_products(o.val_dtype, o.accum_f64)), kChunkRows, chunks);
     chunks.push_back((int32_t)A->n);
     h->nchunks = (int64_t)chunks.size() - 1;
     const std::vector<int32_t> desc = chunk_descriptors(chunks, rp.data());

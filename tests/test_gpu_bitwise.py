@@ -15,7 +15,8 @@ equal bit for bit:
   the rounded values of P A P^T.
 
 Rows longer than one chunk (MPK: 4096 stored entries at k = 1, 1024 at
-k = 2, 4096/k for k >= 4; baseline SpMV: 3072 at k = 1, otherwise the same)
+k = 2, 4096/k for k >= 4; baseline SpMV: 3072 at k = 1, 2048 at k = 2 with
+FP32 products, otherwise the same)
 are reduced by a tree and are not covered here; none of these matrices has
 one.  The recurrence
 epilogue (Chebyshev) keeps its 1e-12 bar in the other tests."""
