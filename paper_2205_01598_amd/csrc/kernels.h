@@ -301,9 +301,10 @@ __device__ __forceinline__ void chunk_gather(const int4 d, const ChunkRegs<VT, K
     gx.pre = Col2Ops{};
     gx.pre2 = Col2Ops{};
     if constexpr (K == 2 && REC) {
-        // a chunk of up to 2048 / 2 nonzeros usually has at most 256 rows,
-        // i.e. at most two outputs per thread: both have their operands
-        // loaded here, so none is loaded after the row sums
+        // a chunk of 8 products per thread (1024 nonzeros at k = 2) usually
+        // has at most 256 rows, i.e. at most two outputs per thread: both
+        // have their operands loaded here, so none is loaded after the row
+        // sums (with 16 products further outputs load theirs in phase 2)
         if (tid < nr * 2) gx.pre = col2_operands<COH>(d.x + (tid >> 1), tid & 1, x, yq2, q, rec);
         if (tid + kBlock < nr * 2)
             gx.pre2 = col2_operands<COH>(d.x + ((tid + kBlock) >> 1), tid & 1, x, yq2, q, rec);
