@@ -130,13 +130,13 @@ void append_chunks64(const int64_t *rowptr, int64_t r0, int64_t r1, int64_t max_
 // FP32 arithmetic, takes 16).  For k >= 4 both take 16.  Host (chunk
 // cutting) and device (chunk kernel) use the same values.
 constexpr int32_t mpk_products_per_thread(int32_t k) { return k == 2 ? 8 : 16; }
-constexpr int32_t spmv_products_per_thread(int32_t k, bool fp32_products) {
-    return k == 1 ? 12 : (k == 2 && !fp32_products) ? 8 : 16;
+constexpr int32_t spmv_products_per_thread(int32_t k, bool f32_products) {
+    return k == 1 ? 12 : (k == 2 && !f32_products) ? 8 : 16;
 }
 // Nonzeros per kernel chunk for k right-hand sides.
 constexpr int32_t mpk_chunk_nnz(int32_t k) { return 256 * mpk_products_per_thread(k) / k; }
-constexpr int32_t spmv_chunk_nnz(int32_t k, bool fp32_products) {
-    return 256 * spmv_products_per_thread(k, fp32_products) / k;
+constexpr int32_t spmv_chunk_nnz(int32_t k, bool f32_products) {
+    return 256 * spmv_products_per_thread(k, f32_products) / k;
 }
 // FP32 products: FP32 or BF16 values without accum_f64
 constexpr bool fp32_products(int32_t val_dtype, int32_t accum_f64) { return val_dtype != MPK_F64 && !accum_f64; }
