@@ -315,13 +315,26 @@ def _greedy_chunks(rp, r0, r1, max_nnz, max_rows=1024):
     return out
 
 
+def _tile_cases():
+    yield "27pt_20", W.stencil_27pt_random(20, seed=3)[0]
+    # power-law rows, some longer than a chunk, and a dense row
+    Z = W.zipf_rows(6000, 1.5, seed=2, cap=5000)
+    yield "zipf_long_rows", W.CSR(Z.n, Z.rowptr, Z.col, Z.val)
+    # most rows empty except the diagonal of every tenth row
+    n = 30000
+    d = np.arange(0, n, 10)
+    rp = np.zeros(n + 1, np.int64)
+    rp[d + 1] = 1
+    yield "sparse_rows", W.CSR(n, np.cumsum(rp), d.astype(np.int32), np.ones(len(d)))
+
+
+@pytest.mark.parametrize("name,A", list(_tile_cases()), ids=[c[0] for c in _tile_cases()])
 @pytest.mark.parametrize("k,tile", [(1, 8192), (1, 12288), (1, 6000), (2, 4096), (4, 4096), (1, 1000)])
-def test_tiles_are_runs_of_whole_chunks(k, tile):
+def test_tiles_are_runs_of_whole_chunks(name, A, k, tile):
     # A tile of at least one kernel chunk (4096 nonzeros at k = 1, 1024 at
     # k = 2, 4096/k for k >= 4, include/mpk.h) is a run of whole chunks: its
     # group's rows cut greedily into chunks, round(tile / chunk) chunks per
     # tile, shared out equally.  Smaller tiles split the nonzeros equally.
-    A, _ = W.stencil_27pt_random(20, seed=3)
     pl = Plan(A, 4, 1 << 20, upload=False, root_mode=1, nrhs=k, tile_nnz=tile)
     _, lp, gp, _ = pl.arrays()
     rp = pl.matrix()[0]
